@@ -1,0 +1,179 @@
+"""Throughput of the Taylor--Couette RK3 substep on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                [--precision fp64|mixed] [--no-cpu-baseline]
+
+A step is one full RK3 step (3 substeps: velocity recovery, inverse
+transforms, products, forward transforms, explicit terms, banded solves and
+the mean flow) of the whole grid, on synthetic seeded fields already resident
+in HBM.  value = grid points x substeps per second / 1e6.  Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=30)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="tc-turbulent-fp64")
+    p.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-modes", type=int, default=4096,
+                   help="modes the CPU baseline solves radially (the transforms cover the whole grid)")
+    p.add_argument("--copy-calib", action="store_true",
+                   help="only run a device copy of known size (counter calibration)")
+    return p.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 512 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 5}))
+
+
+def cpu_baseline(w, nmodes_sample):
+    """The FP64 oracle on the host: one substep of the same workload, with the
+    transforms over the whole grid and the per-mode radial work on a sample of
+    modes, scaled to all modes."""
+    from oracle import Geometry, Oracle
+    from paper_0711_1429_amd.synth import initial_fields
+
+    geo = Geometry(zeta=w["zeta"], re=w["re"], nr=w["nr"], ntheta=w["ntheta"], nz=w["nz"],
+                   dt=w["dt"], stretch=w["stretch"])
+    orc = Oracle(geo)
+    orc.load(*initial_fields(orc.disc.r, w["zeta"], w["ntheta"], w["nz"], w["amplitude"], w["seed"]))
+    idx = np.flatnonzero(~orc.mc.is_mean)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(idx, size=min(nmodes_sample, idx.size), replace=False))
+    t0 = time.perf_counter()
+    dv, u, ww, c = orc.velocity()
+    P = orc.products(u, orc.v, ww)
+    t1 = time.perf_counter()
+    nv, ne = orc.explicit_terms(sample, u, orc.v, ww, c, P)
+    orc.radial_update(0, sample, orc.v, orc.eta, nv, ne, orc.nv_prev[:, sample], orc.neta_prev[:, sample])
+    t2 = time.perf_counter()
+    t_sub = (t1 - t0) + (t2 - t1) * idx.size / sample.size
+    pts = w["nr"] * w["ntheta"] * w["nz"] / 1e6
+    return {
+        "value": pts / t_sub,
+        "unit": "Mpts*substeps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one substep of {w['nr']}x{w['ntheta']}x{w['nz']}: recovery and dealiased "
+                   f"products on the whole grid ({t1 - t0:.1f} s), explicit terms and banded solves "
+                   f"on {sample.size} of {idx.size} modes ({t2 - t1:.1f} s) scaled to all modes; "
+                   f"numpy FFT and LAPACK banded solves run single-threaded "
+                   f"(host reports {os.cpu_count()} CPUs)"),
+        "seconds_per_substep": t_sub,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "the solver holds the whole grid in one GPU's HBM", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calib:
+        copy_calibration()
+        return
+    from paper_0711_1429_amd import tc
+    from paper_0711_1429_amd.synth import WORKLOADS, initial_fields
+
+    w = dict(WORKLOADS[args.workload])
+    prec = tc.TC_PREC_MIXED if args.precision == "mixed" else tc.TC_PREC_FP64
+    solver = tc.Solver(tc.make_geometry(zeta=w["zeta"], re=w["re"], nr=w["nr"], ntheta=w["ntheta"],
+                                        nz=w["nz"], dt=w["dt"], stretch=w["stretch"], precision=prec))
+    r = solver.grid()
+    solver.load_fields(*initial_fields(r, w["zeta"], w["ntheta"], w["nz"], w["amplitude"], w["seed"]))
+    print(f"bench: {args.workload} {args.precision} warmup {args.warmup}", file=sys.stderr, flush=True)
+    solver.step(args.warmup)
+
+    try:
+        import torch
+        sync = torch.cuda.synchronize if torch.cuda.is_available() else (lambda: None)
+    except ImportError:  # pragma: no cover
+        sync = lambda: None  # noqa: E731
+
+    # timed region; per-kernel HIP events on the solver's stream are recorded
+    # inside it (one event pair per launch)
+    solver.timing(True)
+    sync()
+    t0 = time.perf_counter()
+    solver.step(args.steps)
+    sync()
+    elapsed = time.perf_counter() - t0
+    ktimes = solver.kernel_times()
+    solver.timing(False)
+    print(f"bench: timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    substeps = 3 * args.steps
+    pts = w["nr"] * w["ntheta"] * w["nz"]
+    value = pts * substeps / elapsed / 1e6
+    kbytes = solver.kernel_bytes()
+    per_kernel = {}
+    for name, (ms, calls) in ktimes.items():
+        if calls:
+            avg = ms / calls
+            per_kernel[name] = {"avg_ms": avg, "calls": calls,
+                                "model_GBs": kbytes[name] / (avg * 1e-3) / 1e9}
+    step_kernels = ("radial_derivative", "zfft_inverse", "theta_rows_products", "zfft_forward",
+                    "radial_rhs", "radial_solve")
+    dom = max(step_kernels, key=lambda k: per_kernel.get(k, {}).get("avg_ms", 0.0) * per_kernel.get(k, {}).get("calls", 0))
+    dk = per_kernel[dom]
+    achieved = kbytes[dom] / (dk["avg_ms"] * 1e-3) / 1e9
+    # whole-substep byte model: each stage reads and writes HBM once
+    nr, nj, nl, nz = w["nr"], (w["ntheta"] - 1) // 3 + 1, 2 * ((w["nz"] - 1) // 3) + 1, w["nz"]
+    S = nr * nj * nl
+    Q = nr * nz * nj
+    model = (448 * S + 288 * Q) if prec == tc.TC_PREC_FP64 else (304 * S + 144 * Q)
+    t_sub = elapsed / substeps
+    out = {
+        "metric": "Mpts*RK3 substeps/s on 1 GPU (FP64 vs mixed at stated L2 error); HBM GB/s",
+        "value": value,
+        "unit": "Mpts*substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == tc.TC_PREC_FP64 else "f32-transforms/f64-radial",
+        "data": "synthetic: laminar Couette profile plus seeded random-phase divergence-free perturbation",
+        "config": {"workload": args.workload, "nr": w["nr"], "ntheta": w["ntheta"], "nz": w["nz"],
+                   "zeta": w["zeta"], "re": w["re"], "dt": w["dt"], "stretch": w["stretch"],
+                   "precision": args.precision},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "substep_model": {"bytes": model, "ms_per_substep": t_sub * 1e3,
+                          "GBs": model / t_sub / 1e9, "frac": model / t_sub / 1e9 / HBM_PEAK_GBS},
+        "kernels": per_kernel,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_modes)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,102 @@
+// Device-side data of one instance and the launchers of the substep kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "host_setup.h"
+
+namespace tc {
+
+template <typename T>
+struct C {
+    T x, y;
+};
+
+struct FftPlanDev {
+    int n;
+    int npass;
+    int radix[MAX_RADICES];
+};
+
+// Read-only per-instance tables on the device, passed by value to kernels.
+struct DevGeom {
+    int nr, nj, nl, kt, kz, ntheta, nz;
+    int P;            // nj * nl modes per radial plane
+    int mean;         // index of the (0,0) mode within a plane (= kz)
+    int npairs;       // nj * (kz + 1)
+    double nu, w_outer;
+    const double* r;        // [nr]
+    const int* sigma;       // [nr]
+    const double* coef;     // [5][nr][5]
+    const double* blu;      // [nr][5]
+    const double* m;        // [nj]
+    const double* alpha;    // [nl]
+    const double* tw_theta; // [ntheta] complex
+    const double* tw_z;     // [nz] complex
+    const float* tw_theta_f;
+    const float* tw_z_f;
+    const double* wr;       // [nr] trapezoid weight * r
+    FftPlanDev plan_theta, plan_z;
+};
+
+// Coefficients of one substep of the low-storage RK3 / Crank--Nicolson scheme.
+struct StepCoef {
+    double dt;       // time step
+    double gamma;    // weight of N^{k-1}
+    double rho;      // weight of N^{k-2}
+    double bdt_nu;   // beta_k dt nu
+};
+
+// Device buffers of one instance.  c128 arrays are [nr][nj][nl].
+struct DevBuf {
+    C<double>* v;
+    C<double>* eta;
+    C<double>* nv;     // explicit-term register of v (mean slot: mean axial)
+    C<double>* neta;   // explicit-term register of eta (mean slot: mean azimuthal)
+    C<double>* dv;     // radial derivative of v
+    C<double>* rv;     // right-hand side / forward-elimination values of v
+    C<double>* re;     // the same for eta
+    double* umean;
+    double* wmean;
+    void* zb;          // [3][nr][nz][nj]  after the inverse z transform (T)
+    void* pb;          // [6][nr][nz][nj]  products after the forward theta transform (T)
+    void* ps;          // [6][nr][nj][nl]  product spectra (T)
+    double* fac;       // [2][3][nr][npairs] elimination factors
+    double* partial;   // reduction partials
+    int* flags;        // reduction flags
+    double* stats;     // [16] statistics
+    int partial_n;     // capacity of partial (doubles) / flags (ints)
+};
+
+enum KernelId {
+    K_DV = 0,
+    K_ZINV,
+    K_THETA,
+    K_ZFWD,
+    K_RHS,
+    K_SOLVE,
+    K_ENERGY,
+    K_FINITE,
+    K_COUNT
+};
+
+extern const char* const kKernelNames[K_COUNT];
+
+void launch_dv(const DevGeom& g, const DevBuf& b, hipStream_t s);
+void launch_zinv(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
+void launch_theta(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
+void launch_zfwd(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
+void launch_rhs(const DevGeom& g, const DevBuf& b, bool fp32, const StepCoef& c, hipStream_t s);
+void launch_solve(const DevGeom& g, const DevBuf& b, const StepCoef& c, hipStream_t s);
+// spectral u, w of the current state (needs b.dv up to date)
+void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>* w, hipStream_t s);
+// energy reductions + finite check + statistics into b.stats
+void launch_stats(const DevGeom& g, const DevBuf& b, hipStream_t s);
+// finite check of the state into b.flags[0]
+void launch_finite(const DevGeom& g, const DevBuf& b, hipStream_t s);
+
+// Launch-shape helpers shared by the host code (buffer sizing).
+int zcols_per_block(int nz, int nj);
+int reduction_blocks(const DevGeom& g);
+
+}  // namespace tc

@@ -1,0 +1,961 @@
+// HIP kernels (gfx950) of one RK3 / Crank--Nicolson substep of the
+// Taylor--Couette DNS (Pirro & Quadrio; Sec. 2.1 and Appendix).
+//
+// Spectral fields are [r][j][l + K_z] complex (plane-major), so every radial
+// sweep reads consecutive modes with consecutive lanes.  Per substep:
+//
+//   k_dv     velocity recovery, radial part: D v from the compact derivative
+//            (d0 D v = d1 v, pentadiagonal, one mode per lane).
+//   k_zinv   u, v, w per (r, j-column block): recovery of u and w from
+//            (v, eta, D v) in FP64, zero-padded inverse z FFT in LDS, written
+//            transposed as [field][r][z][j].
+//   k_theta  per (r, z-pair): the two real theta rows of each field packed
+//            as one complex row, inverse FFT, the six products, forward FFT,
+//            unpacked and truncated to j <= K_theta: [product][r][z][j].
+//   k_zfwd   per (r, j-column block): forward z FFT, truncation to |l| <= K_z
+//            and the 1/(N_theta N_z) normalisation: [product][r][j][l].
+//   k_rhs    one (r, mode) per lane: the explicit terms N = nu E + NL of
+//            eq. (final-v) / eq. (final-eta) (and of the mean flow) from
+//            5-point compact stencils, and the Runge--Kutta right-hand side.
+//   k_solve  one (|l|, j) pair and one equation per lane: assembles the real
+//            pentadiagonal Crank--Nicolson matrix on the fly (boundary rows
+//            folded) and eliminates both +l and -l right-hand sides.
+//
+// The FFT stages are templated on the storage type (double, or float for the
+// mixed-precision path); recovery, the radial stages and reductions are FP64.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace tc {
+
+const char* const kKernelNames[K_COUNT] = {
+    "radial_derivative", "zfft_inverse", "theta_rows_products", "zfft_forward",
+    "radial_rhs",        "radial_solve", "stats_energy",        "finite_check"};
+
+namespace {
+
+constexpr int NT = 256;             // threads of the FFT and stencil kernels
+constexpr int ZELEMS = 3072;        // max complex elements per z-FFT block
+constexpr int TELEMS = 3 * MAX_FFT; // max complex elements per theta block
+constexpr int SOLVE_NT = 64;        // lanes per block of the radial solve
+constexpr int RED_NT = 256;         // lanes per block of the reductions
+
+using cd = C<double>;
+
+template <typename T>
+__device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ C<T> cscale(C<T> a, T s) { return {a.x * s, a.y * s}; }
+// i * z
+__device__ __forceinline__ cd ci(cd z) { return {-z.y, z.x}; }
+__device__ __forceinline__ cd cfma(double s, cd a, cd acc) { return {acc.x + s * a.x, acc.y + s * a.y}; }
+
+template <typename T>
+__device__ __forceinline__ C<T> twid(const T* tw, int t, int sign) {
+    C<T> w = {tw[2 * t], tw[2 * t + 1]};
+    if (sign < 0) w.y = -w.y;
+    return w;
+}
+
+// In-register DFT of radix R with exponent sign * 2 pi i / R.
+template <typename T, int R>
+__device__ __forceinline__ void dft(C<T>* x, int sign) {
+    if constexpr (R == 2) {
+        C<T> a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+        const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+        C<T> t1 = cadd(x[1], x[2]);
+        C<T> t2 = csub(x[1], x[2]);
+        C<T> m = {x[0].x - (T)0.5 * t1.x, x[0].y - (T)0.5 * t1.y};
+        T s = sign > 0 ? h : -h;
+        C<T> n = {-s * t2.y, s * t2.x};  // s i t2
+        x[0] = cadd(x[0], t1);
+        x[1] = cadd(m, n);
+        x[2] = csub(m, n);
+    } else {  // R == 4
+        C<T> a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+        C<T> c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
+        C<T> id = sign > 0 ? C<T>{-d.y, d.x} : C<T>{d.y, -d.x};  // sign i d
+        x[0] = cadd(a, c);
+        x[2] = csub(a, c);
+        x[1] = cadd(b, id);
+        x[3] = csub(b, id);
+    }
+}
+
+// One Stockham autosort pass of radix R over ncols columns of length N held
+// in LDS as buf[col * N + i].  Inputs are read into registers, the block
+// synchronises, outputs are written back in place.
+template <typename T, int R, int MAXB>
+__device__ __forceinline__ void fft_pass(C<T>* buf, int ncols, int N, int Ns, int sign, const T* tw) {
+    const int tid = threadIdx.x;
+    const int nbf = N / R;
+    const int total = ncols * nbf;
+    const int step = N / (Ns * R);
+    C<T> y[MAXB][R];
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        const int b = tid + t * NT;
+        if (b < total) {
+            const int col = b / nbf;
+            const int jb = b - col * nbf;
+            const C<T>* base = buf + col * N;
+            C<T> x[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) x[k] = base[jb + k * nbf];
+            const int jm = jb % Ns;
+#pragma unroll
+            for (int k = 1; k < R; ++k) x[k] = cmul(x[k], twid(tw, jm * k * step, sign));
+            dft<T, R>(x, sign);
+#pragma unroll
+            for (int k = 0; k < R; ++k) y[t][k] = x[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXB; ++t) {
+        const int b = tid + t * NT;
+        if (b < total) {
+            const int col = b / nbf;
+            const int jb = b - col * nbf;
+            const int jm = jb % Ns;
+            C<T>* base = buf + col * N;
+            const int idx = (jb / Ns) * Ns * R + jm;
+#pragma unroll
+            for (int k = 0; k < R; ++k) base[idx + k * Ns] = y[t][k];
+        }
+    }
+    __syncthreads();
+}
+
+// Complete FFT of ncols columns (ncols * N <= ELEMS) in LDS; the caller has
+// synchronised after filling buf.  Ends synchronised.
+template <typename T, int ELEMS>
+__device__ void fft_lds(C<T>* buf, int ncols, const FftPlanDev& p, int sign, const T* tw) {
+    int ns = 1;
+    for (int i = 0; i < p.npass; ++i) {
+        const int r = p.radix[i];
+        if (r == 4)
+            fft_pass<T, 4, (ELEMS + 4 * NT - 1) / (4 * NT)>(buf, ncols, p.n, ns, sign, tw);
+        else if (r == 3)
+            fft_pass<T, 3, (ELEMS + 3 * NT - 1) / (3 * NT)>(buf, ncols, p.n, ns, sign, tw);
+        else
+            fft_pass<T, 2, (ELEMS + 2 * NT - 1) / (2 * NT)>(buf, ncols, p.n, ns, sign, tw);
+        ns *= r;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ const T* tw_z(const DevGeom& g);
+template <>
+__device__ __forceinline__ const double* tw_z<double>(const DevGeom& g) { return g.tw_z; }
+template <>
+__device__ __forceinline__ const float* tw_z<float>(const DevGeom& g) { return g.tw_z_f; }
+template <typename T>
+__device__ __forceinline__ const T* tw_t(const DevGeom& g);
+template <>
+__device__ __forceinline__ const double* tw_t<double>(const DevGeom& g) { return g.tw_theta; }
+template <>
+__device__ __forceinline__ const float* tw_t<float>(const DevGeom& g) { return g.tw_theta_f; }
+
+// Wavenumber coefficients at radius R: k^2, a = 1/k^2 and its analytic
+// r-derivatives a1, a2, a3 (s = alpha^2 R^2 + m^2, a = R^2 / s).
+struct Wn {
+    double k2, a, a1, a2, a3;
+};
+__device__ __forceinline__ Wn wavecoef(double m, double al, double R) {
+    const double m2 = m * m, aR2 = al * al * R * R;
+    const double s = aR2 + m2;
+    const double is = 1.0 / s;
+    Wn w;
+    w.k2 = s / (R * R);
+    w.a = R * R * is;
+    w.a1 = 2.0 * m2 * R * is * is;
+    w.a2 = 2.0 * m2 * (m2 - 3.0 * aR2) * is * is * is;
+    w.a3 = -24.0 * m2 * al * al * R * (m2 - aR2) * is * is * is * is;
+    return w;
+}
+
+// u, w from v, eta and D v (continuity and the definition of eta):
+// u = (i alpha D_* v - (i m / R) eta) a,  w = ((i m / R) D_* v + i alpha eta) a.
+__device__ __forceinline__ void recover(cd v, cd eta, cd dv, double R, double m, double al, double a,
+                                        cd& u, cd& w) {
+    const cd ds = {dv.x + v.x / R, dv.y + v.y / R};
+    const double mr = m / R;
+    u.x = (-al * ds.y + mr * eta.y) * a;
+    u.y = (al * ds.x - mr * eta.x) * a;
+    w.x = (-mr * ds.y - al * eta.y) * a;
+    w.y = (mr * ds.x + al * eta.x) * a;
+}
+
+// ---------------------------------------------------------------- k_dv
+__global__ __launch_bounds__(NT) void k_dv(DevGeom g, const cd* __restrict__ v, cd* __restrict__ dv) {
+    const int mode = blockIdx.x * NT + threadIdx.x;
+    if (mode >= g.P) return;
+    const int nr = g.nr;
+    const size_t P = g.P;
+    const double* d0 = g.coef;
+    const double* d1 = g.coef + (size_t)1 * nr * 5;
+    if (mode == g.mean) {
+        for (int n = 0; n < nr; ++n) dv[n * P + mode] = cd{0.0, 0.0};
+        return;
+    }
+    cd e1 = {0.0, 0.0}, el = {0.0, 0.0};
+    for (int j = 0; j < 5; ++j) {
+        e1 = cfma(d1[1 * 5 + j], v[(size_t)(g.sigma[1] + j) * P + mode], e1);
+        el = cfma(d1[(nr - 2) * 5 + j], v[(size_t)(g.sigma[nr - 2] + j) * P + mode], el);
+    }
+    dv[mode] = cd{0.0, 0.0};
+    dv[1 * P + mode] = e1;
+    dv[(size_t)(nr - 2) * P + mode] = el;
+    dv[(size_t)(nr - 1) * P + mode] = cd{0.0, 0.0};
+    cd y1 = {0.0, 0.0}, y2 = {0.0, 0.0};
+    for (int n = 2; n <= nr - 3; ++n) {
+        cd rhs = {0.0, 0.0};
+        for (int j = 0; j < 5; ++j) {
+            const int col = n - 2 + j;
+            rhs = cfma(d1[n * 5 + j], v[(size_t)col * P + mode], rhs);
+            if (col == 1) rhs = cfma(-d0[n * 5 + j], e1, rhs);
+            if (col == nr - 2) rhs = cfma(-d0[n * 5 + j], el, rhs);
+        }
+        const double* L = g.blu + n * 5;
+        cd y = cfma(-L[0], y2, cfma(-L[1], y1, rhs));
+        dv[(size_t)n * P + mode] = y;
+        y2 = y1;
+        y1 = y;
+    }
+    cd x1 = {0.0, 0.0}, x2 = {0.0, 0.0};
+    for (int n = nr - 3; n >= 2; --n) {
+        const double* L = g.blu + n * 5;
+        cd y = dv[(size_t)n * P + mode];
+        cd t = cfma(-L[4], x2, cfma(-L[3], x1, y));
+        cd x = {t.x * L[2], t.y * L[2]};
+        dv[(size_t)n * P + mode] = x;
+        x2 = x1;
+        x1 = x;
+    }
+}
+
+// ---------------------------------------------------------------- k_zinv
+template <typename T>
+__global__ __launch_bounds__(NT) void k_zinv(DevGeom g, const cd* __restrict__ v, const cd* __restrict__ eta,
+                                             const cd* __restrict__ dv, const double* __restrict__ umean,
+                                             const double* __restrict__ wmean, C<T>* __restrict__ zb, int jb) {
+    extern __shared__ __align__(16) char smem_raw[];
+    C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+    const int r = blockIdx.y;
+    const int j0 = blockIdx.x * jb;
+    const int nz = g.nz, kz = g.kz, nl = g.nl, nj = g.nj;
+    const int ncols = min(jb, nj - j0);
+    const double R = g.r[r];
+    const size_t P = g.P;
+    const T* tw = tw_z<T>(g);
+    for (int f = 0; f < 3; ++f) {
+        for (int idx = threadIdx.x; idx < ncols * nz; idx += NT) {
+            const int col = idx / nz;
+            const int q = idx - col * nz;
+            const int l = q <= kz ? q : q - nz;
+            C<T> val = {(T)0, (T)0};
+            if (l >= -kz) {
+                const int j = j0 + col;
+                const size_t e = (size_t)r * P + (size_t)j * nl + (l + kz);
+                if (j == 0 && l == 0) {
+                    if (f == 0) val.x = (T)umean[r];
+                    if (f == 2) val.x = (T)wmean[r];
+                } else if (f == 1) {
+                    val = C<T>{(T)v[e].x, (T)v[e].y};
+                } else {
+                    const double m = g.m[j], al = g.alpha[l + kz];
+                    const double a = R * R / (al * al * R * R + m * m);
+                    cd u, w;
+                    recover(v[e], eta[e], dv[e], R, m, al, a, u, w);
+                    const cd s = f == 0 ? u : w;
+                    val = C<T>{(T)s.x, (T)s.y};
+                }
+            }
+            buf[col * nz + q] = val;
+        }
+        __syncthreads();
+        fft_lds<T, ZELEMS>(buf, ncols, g.plan_z, +1, tw);
+        C<T>* out = zb + ((size_t)f * g.nr + r) * nz * nj;
+        for (int idx = threadIdx.x; idx < ncols * nz; idx += NT) {
+            const int z = idx / ncols;
+            const int col = idx - z * ncols;
+            out[(size_t)z * nj + j0 + col] = buf[col * nz + z];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- k_theta
+template <typename T>
+__device__ __forceinline__ C<T> pmul(C<T> a, C<T> b) { return {a.x * b.x, a.y * b.y}; }
+
+// Unpack the forward transforms of packed row pairs and write j = 0..K_theta
+// of rows z0 and z0 + 1 of the products f0..f0+2.
+template <typename T>
+__device__ __forceinline__ void theta_write(const DevGeom& g, const C<T>* buf, C<T>* pb, int r, int z0, int f0) {
+    const int N = g.ntheta, nj = g.nj;
+    for (int idx = threadIdx.x; idx < 3 * nj; idx += NT) {
+        const int f = idx / nj;
+        const int j = idx - f * nj;
+        const C<T> h = buf[f * N + j];
+        const C<T> hm = buf[f * N + (j == 0 ? 0 : N - j)];
+        const C<T> p0 = {(T)0.5 * (h.x + hm.x), (T)0.5 * (h.y - hm.y)};
+        const C<T> p1 = {(T)0.5 * (h.y + hm.y), (T)0.5 * (hm.x - h.x)};
+        C<T>* out = pb + (((size_t)(f0 + f) * g.nr + r) * g.nz + z0) * nj;
+        out[j] = p0;
+        out[nj + j] = p1;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_theta(DevGeom g, const C<T>* __restrict__ zb, C<T>* __restrict__ pb) {
+    extern __shared__ __align__(16) char smem_raw[];
+    C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+    const int r = blockIdx.y;
+    const int z0 = 2 * blockIdx.x;
+    const int N = g.ntheta, kt = g.kt, nj = g.nj, nz = g.nz;
+    const T* tw = tw_t<T>(g);
+    for (int idx = threadIdx.x; idx < 3 * N; idx += NT) {
+        const int f = idx / N;
+        const int p = idx - f * N;
+        const C<T>* row0 = zb + (((size_t)f * g.nr + r) * nz + z0) * nj;
+        const C<T>* row1 = row0 + nj;
+        C<T> h = {(T)0, (T)0};
+        if (p <= kt) {
+            C<T> a = row0[p], b = row1[p];
+            if (p == 0) {
+                a.y = (T)0;
+                b.y = (T)0;
+            }
+            h = C<T>{a.x - b.y, a.y + b.x};
+        } else if (p >= N - kt) {
+            const int jj = N - p;
+            const C<T> a = row0[jj], b = row1[jj];
+            // conj(a) + i conj(b)
+            h = C<T>{a.x + b.y, b.x - a.y};
+        }
+        buf[f * N + p] = h;
+    }
+    __syncthreads();
+    fft_lds<T, TELEMS>(buf, 3, g.plan_theta, +1, tw);
+
+    constexpr int MAXP = MAX_FFT / NT;
+    C<T> keep[MAXP][3];
+#pragma unroll
+    for (int t = 0; t < MAXP; ++t) {
+        const int p = threadIdx.x + t * NT;
+        if (p < N) {
+            const C<T> u = buf[p], vv = buf[N + p], w = buf[2 * N + p];
+            buf[p] = pmul(u, u);
+            buf[N + p] = pmul(u, vv);
+            buf[2 * N + p] = pmul(u, w);
+            keep[t][0] = pmul(vv, vv);
+            keep[t][1] = pmul(vv, w);
+            keep[t][2] = pmul(w, w);
+        }
+    }
+    __syncthreads();
+    fft_lds<T, TELEMS>(buf, 3, g.plan_theta, -1, tw);
+    theta_write<T>(g, buf, pb, r, z0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXP; ++t) {
+        const int p = threadIdx.x + t * NT;
+        if (p < N) {
+            buf[p] = keep[t][0];
+            buf[N + p] = keep[t][1];
+            buf[2 * N + p] = keep[t][2];
+        }
+    }
+    __syncthreads();
+    fft_lds<T, TELEMS>(buf, 3, g.plan_theta, -1, tw);
+    theta_write<T>(g, buf, pb, r, z0, 3);
+}
+
+// ---------------------------------------------------------------- k_zfwd
+template <typename T>
+__global__ __launch_bounds__(NT) void k_zfwd(DevGeom g, const C<T>* __restrict__ pb, C<T>* __restrict__ ps, int jb) {
+    extern __shared__ __align__(16) char smem_raw[];
+    C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+    const int r = blockIdx.y;
+    const int j0 = blockIdx.x * jb;
+    const int nz = g.nz, kz = g.kz, nl = g.nl, nj = g.nj;
+    const int ncols = min(jb, nj - j0);
+    const size_t P = g.P;
+    const T scale = (T)(1.0 / ((double)g.ntheta * (double)g.nz));
+    const T* tw = tw_z<T>(g);
+    for (int f = 0; f < 6; ++f) {
+        const C<T>* in = pb + ((size_t)f * g.nr + r) * nz * nj;
+        for (int idx = threadIdx.x; idx < ncols * nz; idx += NT) {
+            const int z = idx / ncols;
+            const int col = idx - z * ncols;
+            buf[col * nz + z] = in[(size_t)z * nj + j0 + col];
+        }
+        __syncthreads();
+        fft_lds<T, ZELEMS>(buf, ncols, g.plan_z, -1, tw);
+        C<T>* out = ps + (size_t)f * g.nr * P + (size_t)r * P;
+        for (int idx = threadIdx.x; idx < ncols * nl; idx += NT) {
+            const int col = idx / nl;
+            const int li = idx - col * nl;
+            const int l = li - kz;
+            const int q = l < 0 ? l + nz : l;
+            out[(size_t)(j0 + col) * nl + li] = cscale(buf[col * nz + q], scale);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- k_rhs
+template <typename TP>
+__device__ __forceinline__ cd ldp(const C<TP>* p, size_t i) {
+    const C<TP> x = p[i];
+    return cd{(double)x.x, (double)x.y};
+}
+
+template <typename TP>
+__global__ __launch_bounds__(NT) void k_rhs(DevGeom g, DevBuf b, const C<TP>* __restrict__ ps, StepCoef sc) {
+    const size_t gid = (size_t)blockIdx.x * NT + threadIdx.x;
+    const size_t P = g.P;
+    const int nr = g.nr;
+    if (gid >= (size_t)nr * P) return;
+    const int n = (int)(gid / P);
+    const int mode = (int)(gid - (size_t)n * P);
+    const size_t S = (size_t)nr * P;
+    const double* d0 = g.coef + ((size_t)0 * nr + n) * 5;
+    const double* d1 = g.coef + ((size_t)1 * nr + n) * 5;
+    const double* d2 = g.coef + ((size_t)2 * nr + n) * 5;
+    const double* d2s = g.coef + ((size_t)3 * nr + n) * 5;
+    const double* d4s = g.coef + ((size_t)4 * nr + n) * 5;
+    const int s = g.sigma[n];
+    const double bdt = sc.bdt_nu, nu = g.nu;
+
+    if (mode == g.mean) {
+        cd rv = {0.0, 0.0}, re = {0.0, 0.0};
+        if (n >= 1 && n <= nr - 2) {
+            double iu = 0, iw = 0, fu = 0, fw = 0;
+            for (int jj = 0; jj < 5; ++jj) {
+                const int m = s + jj;
+                const double R = g.r[m];
+                const double um = b.umean[m], wm = b.wmean[m];
+                const double uv = (double)ps[1 * S + (size_t)m * P + mode].x;
+                const double vw = (double)ps[4 * S + (size_t)m * P + mode].x;
+                iu += d0[jj] * (um + bdt * um / (R * R)) + d2s[jj] * (bdt * um);
+                iw += d0[jj] * wm + d2s[jj] * (bdt * wm);
+                fu -= d1[jj] * uv + d0[jj] * (uv / R);
+                fw -= d1[jj] * vw + d0[jj] * (2.0 * vw / R);
+            }
+            const double pu = b.nv[gid].x, pw = b.neta[gid].x;
+            rv.x = iu + sc.dt * (sc.gamma * fu + sc.rho * pu);
+            re.x = iw + sc.dt * (sc.gamma * fw + sc.rho * pw);
+            b.nv[gid] = cd{fu, 0.0};
+            b.neta[gid] = cd{fw, 0.0};
+        }
+        b.rv[gid] = rv;
+        b.re[gid] = re;
+        return;
+    }
+
+    const int j = mode / g.nl;
+    const int li = mode - j * g.nl;
+    const double mm = g.m[j], al = g.alpha[li];
+    const bool vrow = n >= 2 && n <= nr - 3;
+    const bool erow = n >= 1 && n <= nr - 2;
+    cd Iv = {0, 0}, Nv = {0, 0}, Ie = {0, 0}, Ne = {0, 0};
+    if (erow) {
+        for (int jj = 0; jj < 5; ++jj) {
+            const size_t e = (size_t)(s + jj) * P + mode;
+            const double R = g.r[s + jj];
+            const cd v = b.v[e], eta = b.eta[e], dv = b.dv[e];
+            const cd UU = ldp(ps, e), UV = ldp(ps, S + e), UW = ldp(ps, 2 * S + e);
+            const cd VV = ldp(ps, 3 * S + e), VW = ldp(ps, 4 * S + e), WW = ldp(ps, 5 * S + e);
+            const Wn wc = wavecoef(mm, al, R);
+            cd u, w;
+            recover(v, eta, dv, R, mm, al, wc.a, u, w);
+            const double iR = 1.0 / R, iR2 = iR * iR, iR3 = iR2 * iR;
+            const cd iu = ci(u), iUV = ci(UV), iVW = ci(VW);
+            // eta equation (eq. (final-eta))
+            Ie = cfma(d0[jj] * (1.0 - bdt * wc.k2), eta, Ie);
+            Ie = cfma(d2s[jj] * bdt, eta, Ie);
+            cd n0 = cfma(4.0 * nu * mm * iR3, iu, cd{0, 0});
+            n0 = cfma(2.0 * nu * mm * al * iR2, v, n0);
+            n0 = cfma(mm * al * iR, UU, n0);
+            n0 = cfma(-2.0 * mm * iR2, iUV, n0);
+            n0 = cfma(mm * mm * iR2 - al * al, UW, n0);
+            n0 = cfma(-al * mm * iR, WW, n0);
+            n0 = cfma(2.0 * al * iR, iVW, n0);
+            cd n1 = cfma(2.0 * nu * mm * iR2, iu, cd{0, 0});
+            n1 = cfma(-mm * iR, iUV, n1);
+            n1 = cfma(al, iVW, n1);
+            Ne = cfma(d0[jj], n0, Ne);
+            Ne = cfma(d1[jj], n1, Ne);
+            if (vrow) {
+                // v equation (eq. (final-v))
+                const cd c = {-al * u.y - mm * iR * w.y, al * u.x + mm * iR * w.x};  // i alpha u + i (m/R) w
+                const cd iw = ci(w);
+                Iv = cfma(d0[jj] * (1.0 - bdt * wc.k2), v, Iv);
+                Iv = cfma(d1[jj] * (wc.a1 + bdt * (wc.a2 * iR + wc.a3 - wc.a1 * iR2 - 2.0 * mm * mm * wc.a * iR3)), v, Iv);
+                Iv = cfma(d2s[jj] * (-wc.a + bdt * (2.0 - 2.0 * wc.a1 * iR)), v, Iv);
+                Iv = cfma(d4s[jj] * (-bdt * wc.a), v, Iv);
+                cd v0 = cfma(-2.0 * nu * mm * iR2, iw, cd{0, 0});
+                v0 = cfma(-al, iUV, v0);
+                v0 = cfma(-mm * iR, iVW, v0);
+                v0 = cfma(-iR, VV, v0);
+                v0 = cfma(iR, WW, v0);
+                cd v1 = cfma(2.0 * nu * mm * (wc.a * iR3 - wc.a1 * iR2), iw, cd{0, 0});
+                v1 = cfma(al * wc.a1, iUV, v1);
+                v1 = cfma(mm * (wc.a1 * iR - 3.0 * wc.a * iR2), iVW, v1);
+                v1 = cfma(wc.a * al * al, UU, v1);
+                v1 = cfma(wc.a * 2.0 * al * mm * iR, UW, v1);
+                v1 = cfma(wc.a * mm * mm * iR2, WW, v1);
+                v1 = cfma(-1.0, VV, v1);
+                cd v2 = cfma(2.0 * nu * mm * wc.a * iR2, iw, cd{0, 0});
+                v2 = cfma(-mm * wc.a * iR, iVW, v2);
+                cd v2s = cfma(-3.0 * nu * wc.a1, c, cd{0, 0});
+                v2s = cfma(-al * wc.a, iUV, v2s);
+                Nv = cfma(d0[jj], v0, Nv);
+                Nv = cfma(d1[jj], v1, Nv);
+                Nv = cfma(d2[jj], v2, Nv);
+                Nv = cfma(d2s[jj], v2s, Nv);
+            }
+        }
+    }
+    cd rv = {0, 0}, re = {0, 0};
+    if (vrow) {
+        const cd pv = b.nv[gid];
+        rv = cfma(sc.dt * sc.gamma, Nv, cfma(sc.dt * sc.rho, pv, Iv));
+    }
+    if (erow) {
+        const cd pe = b.neta[gid];
+        re = cfma(sc.dt * sc.gamma, Ne, cfma(sc.dt * sc.rho, pe, Ie));
+    }
+    b.nv[gid] = vrow ? Nv : cd{0, 0};
+    b.neta[gid] = erow ? Ne : cd{0, 0};
+    b.rv[gid] = rv;
+    b.re[gid] = re;
+}
+
+// ---------------------------------------------------------------- k_solve
+enum { SYS_V = 0, SYS_ETA = 1, SYS_UMEAN = 2, SYS_WMEAN = 3 };
+
+// Row i (1..nr-2) of the Crank--Nicolson matrix M - beta dt nu L in the
+// unknowns 1..nr-2: E[3 + k] is the entry of column i + k (k = -3..3); the
+// wall columns 0 and nr-1 are returned separately in w0, wn.
+__device__ __forceinline__ void lhs_row(const DevGeom& g, int sys, double mm, double al, double bdt, int i,
+                                        double E[7], double& w0, double& wn) {
+    const int nr = g.nr;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) E[k] = 0.0;
+    w0 = wn = 0.0;
+    if (sys == SYS_V && (i == 1 || i == nr - 2)) {
+        // v wall-derivative rows: sum_j d1[wall][j] v_{sigma+j} = 0
+        const int wall = i == 1 ? 0 : nr - 1;
+        const int s = g.sigma[wall];
+        const double* d1 = g.coef + ((size_t)1 * nr + wall) * 5;
+        for (int jj = 0; jj < 5; ++jj) {
+            const int col = s + jj;
+            if (col == 0) w0 += d1[jj];
+            else if (col == nr - 1) wn += d1[jj];
+            else E[col - i + 3] += d1[jj];
+        }
+        return;
+    }
+    const int s = g.sigma[i];
+    const double* d0 = g.coef + ((size_t)0 * nr + i) * 5;
+    const double* d1 = g.coef + ((size_t)1 * nr + i) * 5;
+    const double* d2s = g.coef + ((size_t)3 * nr + i) * 5;
+    const double* d4s = g.coef + ((size_t)4 * nr + i) * 5;
+    for (int jj = 0; jj < 5; ++jj) {
+        const int col = s + jj;
+        const double R = g.r[col];
+        double cf;
+        if (sys == SYS_V) {
+            const Wn wc = wavecoef(mm, al, R);
+            const double iR = 1.0 / R;
+            cf = d0[jj] * (1.0 + bdt * wc.k2)
+               + d1[jj] * (wc.a1 - bdt * (wc.a2 * iR + wc.a3 - wc.a1 * iR * iR - 2.0 * mm * mm * wc.a * iR * iR * iR))
+               + d2s[jj] * (-wc.a - bdt * (2.0 - 2.0 * wc.a1 * iR))
+               + d4s[jj] * (bdt * wc.a);
+        } else if (sys == SYS_ETA) {
+            const double k2 = (al * al * R * R + mm * mm) / (R * R);
+            cf = d0[jj] * (1.0 + bdt * k2) - d2s[jj] * bdt;
+        } else if (sys == SYS_UMEAN) {
+            cf = d0[jj] * (1.0 - bdt / (R * R)) - d2s[jj] * bdt;
+        } else {
+            cf = d0[jj] - d2s[jj] * bdt;
+        }
+        if (col == 0) w0 += cf;
+        else if (col == nr - 1) wn += cf;
+        else E[col - i + 3] += cf;
+    }
+}
+
+__global__ __launch_bounds__(SOLVE_NT) void k_solve(DevGeom g, DevBuf b, StepCoef sc) {
+    const int pair = blockIdx.x * SOLVE_NT + threadIdx.x;
+    if (pair >= g.npairs) return;
+    const int eqn = blockIdx.y;  // 0: v (or mean axial), 1: eta (or mean azimuthal)
+    const int nr = g.nr, kz = g.kz, nl = g.nl;
+    const size_t P = g.P;
+    const int j = pair / (kz + 1);
+    const int lp = pair - j * (kz + 1);
+    const int modeA = j * nl + kz + lp;
+    const int modeB = j * nl + kz - lp;
+    const bool two = lp > 0;
+    const bool mean = (j == 0 && lp == 0);
+    const int sys = mean ? (eqn == 0 ? SYS_UMEAN : SYS_WMEAN) : (eqn == 0 ? SYS_V : SYS_ETA);
+    const double mm = g.m[j], al = g.alpha[kz + lp];
+    const double q0 = sys == SYS_WMEAN ? 1.0 : 0.0;
+    const double qn = sys == SYS_WMEAN ? g.w_outer : 0.0;
+    cd* rhs = eqn == 0 ? b.rv : b.re;
+    const double bdt = sc.bdt_nu;
+    double* fac = b.fac + (size_t)eqn * 3 * nr * g.npairs;
+    const size_t fstride = (size_t)nr * g.npairs;
+
+    double id1 = 0, s11 = 0, s21 = 0, id2 = 0, s12 = 0, s22 = 0;
+    cd yA1 = {0, 0}, yA2 = {0, 0}, yB1 = {0, 0}, yB2 = {0, 0};
+    double G[7] = {0, 0, 0, 0, 0, 0, 0};
+    cd gA = {0, 0}, gB = {0, 0};
+    for (int i = 1; i <= nr - 2; ++i) {
+        double E[7], w0, wn;
+        lhs_row(g, sys, mm, al, bdt, i, E, w0, wn);
+        cd rA = rhs[(size_t)i * P + modeA];
+        cd rB = two ? rhs[(size_t)i * P + modeB] : cd{0, 0};
+        rA.x -= w0 * q0 + wn * qn;
+        if (i == 1) {
+            // fold the entry of column 4 with row 2
+            double F[7], f0, fn;
+            lhs_row(g, sys, mm, al, bdt, 2, F, f0, fn);
+            cd r2A = rhs[(size_t)2 * P + modeA];
+            cd r2B = two ? rhs[(size_t)2 * P + modeB] : cd{0, 0};
+            r2A.x -= f0 * q0 + fn * qn;
+            const double f = E[6] / F[5];
+            E[3] -= f * F[2];
+            E[4] -= f * F[3];
+            E[5] -= f * F[4];
+            E[6] = 0.0;
+            rA = cfma(-f, r2A, rA);
+            rB = cfma(-f, r2B, rB);
+        }
+        if (i == nr - 2) {
+            // fold the entry of column nr-5 with the original row nr-3
+            const double f = E[0] / G[1];
+            E[1] -= f * G[2];
+            E[2] -= f * G[3];
+            E[3] -= f * G[4];
+            E[0] = 0.0;
+            rA = cfma(-f, gA, rA);
+            rB = cfma(-f, gB, rB);
+        }
+        if (i == nr - 3) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) G[k] = E[k];
+            gA = rA;
+            gB = rB;
+        }
+        if (i >= 3) {
+            const double l2 = E[1] * id2;
+            E[2] -= l2 * s12;
+            E[3] -= l2 * s22;
+            rA = cfma(-l2, yA2, rA);
+            rB = cfma(-l2, yB2, rB);
+        }
+        if (i >= 2) {
+            const double l1 = E[2] * id1;
+            E[3] -= l1 * s11;
+            E[4] -= l1 * s21;
+            rA = cfma(-l1, yA1, rA);
+            rB = cfma(-l1, yB1, rB);
+        }
+        const double id = 1.0 / E[3];
+        fac[0 * fstride + (size_t)i * g.npairs + pair] = id;
+        fac[1 * fstride + (size_t)i * g.npairs + pair] = E[4];
+        fac[2 * fstride + (size_t)i * g.npairs + pair] = E[5];
+        rhs[(size_t)i * P + modeA] = rA;
+        if (two) rhs[(size_t)i * P + modeB] = rB;
+        id2 = id1; s12 = s11; s22 = s21; yA2 = yA1; yB2 = yB1;
+        id1 = id;  s11 = E[4]; s21 = E[5]; yA1 = rA; yB1 = rB;
+    }
+    cd* out = eqn == 0 ? b.v : b.eta;
+    double* mout = eqn == 0 ? b.umean : b.wmean;
+    cd xA1 = {0, 0}, xA2 = {0, 0}, xB1 = {0, 0}, xB2 = {0, 0};
+    for (int i = nr - 2; i >= 1; --i) {
+        const double id = fac[0 * fstride + (size_t)i * g.npairs + pair];
+        const double s1 = fac[1 * fstride + (size_t)i * g.npairs + pair];
+        const double s2 = fac[2 * fstride + (size_t)i * g.npairs + pair];
+        const cd yA = rhs[(size_t)i * P + modeA];
+        cd tA = cfma(-s2, xA2, cfma(-s1, xA1, yA));
+        const cd xA = {tA.x * id, tA.y * id};
+        if (mean) {
+            mout[i] = xA.x;
+        } else {
+            out[(size_t)i * P + modeA] = xA;
+        }
+        xA2 = xA1;
+        xA1 = xA;
+        if (two) {
+            const cd yB = rhs[(size_t)i * P + modeB];
+            cd tB = cfma(-s2, xB2, cfma(-s1, xB1, yB));
+            const cd xB = {tB.x * id, tB.y * id};
+            out[(size_t)i * P + modeB] = xB;
+            xB2 = xB1;
+            xB1 = xB;
+        }
+    }
+    if (mean) {
+        mout[0] = q0;
+        mout[nr - 1] = qn;
+    } else {
+        out[modeA] = cd{0, 0};
+        out[(size_t)(nr - 1) * P + modeA] = cd{0, 0};
+        if (two) {
+            out[modeB] = cd{0, 0};
+            out[(size_t)(nr - 1) * P + modeB] = cd{0, 0};
+        }
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+// Volume-weighted energy density c_j (|u|^2 + |v|^2 + |w|^2) w_n r_n over
+// all (r, mode), block partial sums in a fixed order; also counts non-finite
+// state values.
+__global__ __launch_bounds__(RED_NT) void k_energy(DevGeom g, DevBuf b) {
+    __shared__ double se[RED_NT], sp[RED_NT];
+    __shared__ int sf[RED_NT];
+    const size_t P = g.P;
+    const size_t total = (size_t)g.nr * P;
+    double e = 0, ep = 0;
+    int bad = 0;
+    for (size_t gid = (size_t)blockIdx.x * RED_NT + threadIdx.x; gid < total; gid += (size_t)gridDim.x * RED_NT) {
+        const int n = (int)(gid / P);
+        const int mode = (int)(gid - (size_t)n * P);
+        const int j = mode / g.nl;
+        const int li = mode - j * g.nl;
+        const double R = g.r[n];
+        const double cj = j == 0 ? 1.0 : 2.0;
+        const cd v = b.v[gid], eta = b.eta[gid];
+        if (!(isfinite(v.x) && isfinite(v.y) && isfinite(eta.x) && isfinite(eta.y))) bad = 1;
+        double d;
+        if (mode == g.mean) {
+            const double um = b.umean[n], wm = b.wmean[n];
+            if (!(isfinite(um) && isfinite(wm))) bad = 1;
+            d = um * um + wm * wm;
+            e += g.wr[n] * d;
+        } else {
+            const double mm = g.m[j], al = g.alpha[li];
+            const double a = R * R / (al * al * R * R + mm * mm);
+            cd u, w;
+            recover(v, eta, b.dv[gid], R, mm, al, a, u, w);
+            d = cj * (u.x * u.x + u.y * u.y + v.x * v.x + v.y * v.y + w.x * w.x + w.y * w.y);
+            e += g.wr[n] * d;
+            ep += g.wr[n] * d;
+        }
+    }
+    se[threadIdx.x] = e;
+    sp[threadIdx.x] = ep;
+    sf[threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = RED_NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            se[threadIdx.x] += se[threadIdx.x + h];
+            sp[threadIdx.x] += sp[threadIdx.x + h];
+            sf[threadIdx.x] |= sf[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        b.partial[2 * blockIdx.x] = se[0];
+        b.partial[2 * blockIdx.x + 1] = sp[0];
+        b.flags[blockIdx.x] = sf[0];
+    }
+}
+
+// Sums the partials in a fixed order and evaluates the wall shear
+// g = |D w - w / r| at both walls from the one-sided compact rows.
+__global__ __launch_bounds__(RED_NT) void k_stats_final(DevGeom g, DevBuf b, int nblocks) {
+    __shared__ double se[RED_NT], sp[RED_NT];
+    __shared__ int sf[RED_NT];
+    double e = 0, ep = 0;
+    int bad = 0;
+    for (int i = threadIdx.x; i < nblocks; i += RED_NT) {
+        e += b.partial[2 * i];
+        ep += b.partial[2 * i + 1];
+        bad |= b.flags[i];
+    }
+    se[threadIdx.x] = e;
+    sp[threadIdx.x] = ep;
+    sf[threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = RED_NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            se[threadIdx.x] += se[threadIdx.x + h];
+            sp[threadIdx.x] += sp[threadIdx.x + h];
+            sf[threadIdx.x] |= sf[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int nr = g.nr;
+        const double* d1 = g.coef + (size_t)1 * nr * 5;
+        double dwi = 0, dwo = 0;
+        for (int jj = 0; jj < 5; ++jj) {
+            dwi += d1[0 * 5 + jj] * b.wmean[g.sigma[0] + jj];
+            dwo += d1[(nr - 1) * 5 + jj] * b.wmean[g.sigma[nr - 1] + jj];
+        }
+        b.stats[0] = fabs(dwi - b.wmean[0] / g.r[0]);
+        b.stats[1] = fabs(dwo - b.wmean[nr - 1] / g.r[nr - 1]);
+        b.stats[2] = se[0];
+        b.stats[3] = sp[0];
+        b.stats[4] = (double)sf[0];
+    }
+}
+
+__global__ __launch_bounds__(RED_NT) void k_finite(DevGeom g, DevBuf b) {
+    __shared__ int sf[RED_NT];
+    const size_t total = (size_t)g.nr * g.P;
+    int bad = 0;
+    for (size_t i = (size_t)blockIdx.x * RED_NT + threadIdx.x; i < total; i += (size_t)gridDim.x * RED_NT) {
+        const cd v = b.v[i], e = b.eta[i];
+        if (!(isfinite(v.x) && isfinite(v.y) && isfinite(e.x) && isfinite(e.y))) bad = 1;
+    }
+    for (int i = blockIdx.x * RED_NT + threadIdx.x; i < g.nr; i += gridDim.x * RED_NT)
+        if (!(isfinite(b.umean[i]) && isfinite(b.wmean[i]))) bad = 1;
+    sf[threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = RED_NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sf[threadIdx.x] |= sf[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b.flags[blockIdx.x] = sf[0];
+}
+
+__global__ void k_flags_final(DevBuf b, int nblocks) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int bad = 0;
+        for (int i = 0; i < nblocks; ++i) bad |= b.flags[i];
+        b.stats[5] = (double)bad;
+    }
+}
+
+// Spectral u and w of every mode (mean profiles in the (0,0) slot).
+__global__ __launch_bounds__(NT) void k_velocity(DevGeom g, DevBuf b, cd* __restrict__ uo, cd* __restrict__ wo) {
+    const size_t gid = (size_t)blockIdx.x * NT + threadIdx.x;
+    const size_t P = g.P;
+    if (gid >= (size_t)g.nr * P) return;
+    const int n = (int)(gid / P);
+    const int mode = (int)(gid - (size_t)n * P);
+    if (mode == g.mean) {
+        uo[gid] = cd{b.umean[n], 0.0};
+        wo[gid] = cd{b.wmean[n], 0.0};
+        return;
+    }
+    const int j = mode / g.nl;
+    const int li = mode - j * g.nl;
+    const double R = g.r[n], mm = g.m[j], al = g.alpha[li];
+    const double a = R * R / (al * al * R * R + mm * mm);
+    cd u, w;
+    recover(b.v[gid], b.eta[gid], b.dv[gid], R, mm, al, a, u, w);
+    uo[gid] = u;
+    wo[gid] = w;
+}
+
+}  // namespace
+
+int zcols_per_block(int nz, int nj) {
+    int jb = ZELEMS / nz;
+    if (jb < 1) jb = 1;
+    if (jb > nj) jb = nj;
+    return jb;
+}
+
+int reduction_blocks(const DevGeom& g) {
+    const size_t total = (size_t)g.nr * g.P;
+    size_t nb = (total + RED_NT - 1) / RED_NT;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
+void launch_dv(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    dim3 grid((g.P + NT - 1) / NT);
+    hipLaunchKernelGGL(k_dv, grid, dim3(NT), 0, s, g, b.v, b.dv);
+}
+
+void launch_zinv(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
+    const int jb = zcols_per_block(g.nz, g.nj);
+    dim3 grid((g.nj + jb - 1) / jb, g.nr);
+    if (fp32) {
+        size_t lds = (size_t)jb * g.nz * sizeof(C<float>);
+        hipLaunchKernelGGL(k_zinv<float>, grid, dim3(NT), lds, s, g, b.v, b.eta, b.dv, b.umean, b.wmean,
+                           (C<float>*)b.zb, jb);
+    } else {
+        size_t lds = (size_t)jb * g.nz * sizeof(C<double>);
+        hipLaunchKernelGGL(k_zinv<double>, grid, dim3(NT), lds, s, g, b.v, b.eta, b.dv, b.umean, b.wmean,
+                           (C<double>*)b.zb, jb);
+    }
+}
+
+void launch_theta(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
+    dim3 grid(g.nz / 2, g.nr);
+    if (fp32) {
+        size_t lds = (size_t)3 * g.ntheta * sizeof(C<float>);
+        hipLaunchKernelGGL(k_theta<float>, grid, dim3(NT), lds, s, g, (const C<float>*)b.zb, (C<float>*)b.pb);
+    } else {
+        size_t lds = (size_t)3 * g.ntheta * sizeof(C<double>);
+        hipLaunchKernelGGL(k_theta<double>, grid, dim3(NT), lds, s, g, (const C<double>*)b.zb, (C<double>*)b.pb);
+    }
+}
+
+void launch_zfwd(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
+    const int jb = zcols_per_block(g.nz, g.nj);
+    dim3 grid((g.nj + jb - 1) / jb, g.nr);
+    if (fp32) {
+        size_t lds = (size_t)jb * g.nz * sizeof(C<float>);
+        hipLaunchKernelGGL(k_zfwd<float>, grid, dim3(NT), lds, s, g, (const C<float>*)b.pb, (C<float>*)b.ps, jb);
+    } else {
+        size_t lds = (size_t)jb * g.nz * sizeof(C<double>);
+        hipLaunchKernelGGL(k_zfwd<double>, grid, dim3(NT), lds, s, g, (const C<double>*)b.pb, (C<double>*)b.ps, jb);
+    }
+}
+
+void launch_rhs(const DevGeom& g, const DevBuf& b, bool fp32, const StepCoef& c, hipStream_t s) {
+    const size_t total = (size_t)g.nr * g.P;
+    dim3 grid((unsigned)((total + NT - 1) / NT));
+    if (fp32)
+        hipLaunchKernelGGL(k_rhs<float>, grid, dim3(NT), 0, s, g, b, (const C<float>*)b.ps, c);
+    else
+        hipLaunchKernelGGL(k_rhs<double>, grid, dim3(NT), 0, s, g, b, (const C<double>*)b.ps, c);
+}
+
+void launch_solve(const DevGeom& g, const DevBuf& b, const StepCoef& c, hipStream_t s) {
+    dim3 grid((g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2);
+    hipLaunchKernelGGL(k_solve, grid, dim3(SOLVE_NT), 0, s, g, b, c);
+}
+
+void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>* w, hipStream_t s) {
+    const size_t total = (size_t)g.nr * g.P;
+    hipLaunchKernelGGL(k_velocity, dim3((unsigned)((total + NT - 1) / NT)), dim3(NT), 0, s, g, b, u, w);
+}
+
+void launch_stats(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    const int nb = reduction_blocks(g);
+    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(RED_NT), 0, s, g, b);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(RED_NT), 0, s, g, b, nb);
+}
+
+void launch_finite(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    const int nb = reduction_blocks(g);
+    hipLaunchKernelGGL(k_finite, dim3(nb), dim3(RED_NT), 0, s, g, b);
+    hipLaunchKernelGGL(k_flags_final, dim3(1), dim3(64), 0, s, b, nb);
+}
+
+}  // namespace tc

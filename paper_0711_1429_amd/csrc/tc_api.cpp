@@ -1,0 +1,606 @@
+// C ABI of libtc.so (declared in include/tc.h): contexts, device memory,
+// field I/O with validation, the substep sequence and statistics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tc.h"
+#include "host_setup.h"
+#include "kernels.h"
+
+using namespace tc;
+
+namespace {
+
+// Low-storage RK3 coefficients (reading of Sec. 2.1 / Sec. 3.1: the paper
+// names a 3-substep Runge--Kutta scheme with Crank--Nicolson viscous terms
+// but prints no coefficients): gamma, rho and the Crank--Nicolson weight
+// beta = (gamma + rho) / 2 of each substep.
+constexpr double kGamma[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+constexpr double kRho[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+
+struct Instance {
+    Setup s;
+    DevGeom g{};
+    DevBuf b{};
+    std::vector<void*> allocs;
+    double time = 0.0;
+    long long steps = 0;
+    int red_blocks = 1;
+};
+
+struct TimedLaunch {
+    int id;
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct tc_ctx {
+    std::vector<Instance> inst;
+    bool dryrun = false;
+    bool fp32 = false;
+    hipStream_t own = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[K_COUNT] = {};
+    long long calls[K_COUNT] = {};
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(tc_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(tc_ctx* c, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, e == hipErrorOutOfMemory ? TC_ENOMEM : TC_EDEVICE, m);
+}
+
+#define HIPCHK(ctx, call)                                  \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+hipEvent_t take_event(tc_ctx* c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs fn() (which launches kernel `id` on c->stream), bracketed by events
+// when timing is on.
+template <typename F>
+void timed(tc_ctx* c, int id, F fn) {
+    if (!c->timing) {
+        fn();
+        return;
+    }
+    TimedLaunch t{id, take_event(c), take_event(c)};
+    if (t.start) (void)hipEventRecord(t.start, c->stream);
+    fn();
+    if (t.stop) (void)hipEventRecord(t.stop, c->stream);
+    c->pending.push_back(t);
+}
+
+void collect_timing(tc_ctx* c) {
+    if (c->pending.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& t : c->pending) {
+        float ms = 0.0f;
+        if (t.start && t.stop && hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+            c->ms[t.id] += ms;
+            c->calls[t.id] += 1;
+        }
+        if (t.start) c->pool.push_back(t.start);
+        if (t.stop) c->pool.push_back(t.stop);
+    }
+    c->pending.clear();
+}
+
+int check_launch(tc_ctx* c, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, what);
+    return TC_OK;
+}
+
+template <typename T>
+int dev_alloc(tc_ctx* c, Instance& in, T** p, size_t count) {
+    void* q = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    in.allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return TC_OK;
+}
+
+template <typename T>
+int upload(tc_ctx* c, Instance& in, const T** p, const std::vector<T>& host) {
+    T* d = nullptr;
+    int rc = dev_alloc(c, in, &d, host.size());
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpy(d, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+    *p = d;
+    return TC_OK;
+}
+
+int alloc_instance(tc_ctx* c, Instance& in) {
+    const Setup& s = in.s;
+    DevGeom& g = in.g;
+    g.nr = s.nr;
+    g.nj = s.nj;
+    g.nl = s.nl;
+    g.kt = s.kt;
+    g.kz = s.kz;
+    g.ntheta = s.ntheta;
+    g.nz = s.nz;
+    g.P = s.nj * s.nl;
+    g.mean = s.kz;
+    g.npairs = s.nj * (s.kz + 1);
+    g.nu = s.nu;
+    g.w_outer = s.w_outer;
+    auto plan = [](const FftPlan& p) {
+        FftPlanDev d{};
+        d.n = p.n;
+        d.npass = p.npass;
+        for (int i = 0; i < MAX_RADICES; ++i) d.radix[i] = p.radix[i];
+        return d;
+    };
+    g.plan_theta = plan(s.plan_theta);
+    g.plan_z = plan(s.plan_z);
+
+    std::vector<double> wr(s.nr);
+    for (int n = 0; n < s.nr; ++n) {
+        double w = n == 0 ? 0.5 * (s.r[1] - s.r[0])
+                 : n == s.nr - 1 ? 0.5 * (s.r[n] - s.r[n - 1])
+                 : 0.5 * (s.r[n + 1] - s.r[n - 1]);
+        wr[n] = w * s.r[n];
+    }
+    std::vector<float> twt(s.tw_theta.begin(), s.tw_theta.end());
+    std::vector<float> twz(s.tw_z.begin(), s.tw_z.end());
+    int rc;
+    if ((rc = upload(c, in, &g.r, s.r))) return rc;
+    if ((rc = upload(c, in, &g.sigma, s.sigma))) return rc;
+    if ((rc = upload(c, in, &g.coef, s.coef))) return rc;
+    if ((rc = upload(c, in, &g.blu, s.blu))) return rc;
+    if ((rc = upload(c, in, &g.m, s.m))) return rc;
+    if ((rc = upload(c, in, &g.alpha, s.alpha))) return rc;
+    if ((rc = upload(c, in, &g.tw_theta, s.tw_theta))) return rc;
+    if ((rc = upload(c, in, &g.tw_z, s.tw_z))) return rc;
+    if ((rc = upload(c, in, &g.tw_theta_f, twt))) return rc;
+    if ((rc = upload(c, in, &g.tw_z_f, twz))) return rc;
+    if ((rc = upload(c, in, &g.wr, wr))) return rc;
+
+    const size_t S = (size_t)s.nr * g.P;
+    const size_t Q = (size_t)s.nr * s.nz * s.nj;
+    const size_t cz = c->fp32 ? sizeof(C<float>) : sizeof(C<double>);
+    DevBuf& b = in.b;
+    C<double>** c128[] = {&b.v, &b.eta, &b.nv, &b.neta, &b.dv, &b.rv, &b.re};
+    for (auto p : c128)
+        if ((rc = dev_alloc(c, in, p, S))) return rc;
+    if ((rc = dev_alloc(c, in, &b.umean, s.nr))) return rc;
+    if ((rc = dev_alloc(c, in, &b.wmean, s.nr))) return rc;
+    char* raw = nullptr;
+    if ((rc = dev_alloc(c, in, &raw, 3 * Q * cz))) return rc;
+    b.zb = raw;
+    if ((rc = dev_alloc(c, in, &raw, 6 * Q * cz))) return rc;
+    b.pb = raw;
+    if ((rc = dev_alloc(c, in, &raw, 6 * S * cz))) return rc;
+    b.ps = raw;
+    if ((rc = dev_alloc(c, in, &b.fac, (size_t)2 * 3 * s.nr * g.npairs))) return rc;
+    in.red_blocks = reduction_blocks(g);
+    b.partial_n = in.red_blocks;
+    if ((rc = dev_alloc(c, in, &b.partial, (size_t)2 * in.red_blocks))) return rc;
+    if ((rc = dev_alloc(c, in, &b.flags, (size_t)in.red_blocks))) return rc;
+    if ((rc = dev_alloc(c, in, &b.stats, 16))) return rc;
+    for (auto p : c128) HIPCHK(c, hipMemset(*p, 0, S * sizeof(C<double>)));
+    HIPCHK(c, hipMemset(b.umean, 0, s.nr * sizeof(double)));
+    HIPCHK(c, hipMemset(b.wmean, 0, s.nr * sizeof(double)));
+    return TC_OK;
+}
+
+void free_instance(Instance& in) {
+    for (void* p : in.allocs) (void)hipFree(p);
+    in.allocs.clear();
+}
+
+Instance* get_inst(tc_ctx* c, int i) {
+    if (!c || i < 0 || i >= (int)c->inst.size()) return nullptr;
+    return &c->inst[i];
+}
+
+int need_device(tc_ctx* c) {
+    if (c->dryrun) return fail(c, TC_EINVAL, "context was created with TC_FLAG_DRYRUN (host only)");
+    return TC_OK;
+}
+
+int run_substep(tc_ctx* c, int k) {
+    for (auto& in : c->inst) {
+        StepCoef sc;
+        sc.dt = in.s.g.dt;
+        sc.gamma = kGamma[k];
+        sc.rho = kRho[k];
+        sc.bdt_nu = 0.5 * (kGamma[k] + kRho[k]) * sc.dt * in.s.nu;
+        const DevGeom& g = in.g;
+        const DevBuf& b = in.b;
+        hipStream_t s = c->stream;
+        timed(c, K_DV, [&] { launch_dv(g, b, s); });
+        timed(c, K_ZINV, [&] { launch_zinv(g, b, c->fp32, s); });
+        timed(c, K_THETA, [&] { launch_theta(g, b, c->fp32, s); });
+        timed(c, K_ZFWD, [&] { launch_zfwd(g, b, c->fp32, s); });
+        timed(c, K_RHS, [&] { launch_rhs(g, b, c->fp32, sc, s); });
+        timed(c, K_SOLVE, [&] { launch_solve(g, b, sc, s); });
+    }
+    return check_launch(c, "substep launch");
+}
+
+int products_only(tc_ctx* c, Instance& in) {
+    hipStream_t s = c->stream;
+    launch_dv(in.g, in.b, s);
+    launch_zinv(in.g, in.b, c->fp32, s);
+    launch_theta(in.g, in.b, c->fp32, s);
+    launch_zfwd(in.g, in.b, c->fp32, s);
+    return check_launch(c, "product launch");
+}
+
+// Host checks of loaded fields (see tc_load_fields in tc.h).
+int validate_fields(tc_ctx* c, const Instance& in, const double* v, const double* eta, const double* um,
+                    const double* wm) {
+    const Setup& s = in.s;
+    const size_t P = (size_t)s.nj * s.nl;
+    const size_t S = (size_t)s.nr * P;
+    for (size_t i = 0; i < 2 * S; ++i)
+        if (!std::isfinite(v[i]) || !std::isfinite(eta[i])) return fail(c, TC_ENONFINITE, "non-finite v or eta");
+    for (int n = 0; n < s.nr; ++n)
+        if (!std::isfinite(um[n]) || !std::isfinite(wm[n]))
+            return fail(c, TC_ENONFINITE, "non-finite mean profile");
+    for (int wall : {0, s.nr - 1})
+        for (size_t i = 0; i < 2 * P; ++i)
+            if (v[2 * wall * P + i] != 0.0 || eta[2 * wall * P + i] != 0.0)
+                return fail(c, TC_ESHAPE, "v and eta must vanish at the walls");
+    const int kz = s.kz;
+    for (int n = 0; n < s.nr; ++n) {
+        const size_t base = 2 * ((size_t)n * P);
+        const size_t mean = base + 2 * (size_t)kz;
+        if (v[mean] != 0.0 || v[mean + 1] != 0.0 || eta[mean] != 0.0 || eta[mean + 1] != 0.0)
+            return fail(c, TC_ESHAPE, "the (0,0) slots of v and eta must be zero (mean flow is separate)");
+        for (int l = 1; l <= kz; ++l) {
+            const size_t p = base + 2 * (size_t)(kz + l), q = base + 2 * (size_t)(kz - l);
+            if (v[p] != v[q] || v[p + 1] != -v[q + 1] || eta[p] != eta[q] || eta[p + 1] != -eta[q + 1])
+                return fail(c, TC_ESHAPE, "the j = 0 column must be Hermitian: f[0][-l] = conj(f[0][l])");
+        }
+    }
+    if (um[0] != 0.0 || um[s.nr - 1] != 0.0) return fail(c, TC_ESHAPE, "u_mean must vanish at both walls");
+    if (wm[0] != 1.0 || wm[s.nr - 1] != s.w_outer)
+        return fail(c, TC_ESHAPE, "w_mean must equal 1 at the inner wall and re_outer/re at the outer wall");
+    return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tc_abi_version(void) { return TC_ABI_VERSION; }
+
+int tc_create(const tc_geometry* g, int n_instances, tc_ctx** out) {
+    g_create_error.clear();
+    if (!g || !out) return fail(nullptr, TC_EINVAL, "null argument");
+    if (n_instances < 1 || n_instances > 4096) return fail(nullptr, TC_EINVAL, "n_instances must be in [1, 4096]");
+    tc_ctx* c = new (std::nothrow) tc_ctx();
+    if (!c) return fail(nullptr, TC_ENOMEM, "host allocation failed");
+    c->dryrun = (g[0].flags & TC_FLAG_DRYRUN) != 0;
+    c->fp32 = g[0].precision == TC_PREC_MIXED;
+    c->inst.resize(n_instances);
+    for (int i = 0; i < n_instances; ++i) {
+        std::string err;
+        if (g[i].precision != g[0].precision || (g[i].flags & TC_FLAG_DRYRUN) != (g[0].flags & TC_FLAG_DRYRUN)) {
+            delete c;
+            return fail(nullptr, TC_EINVAL, "all instances must share precision and flags");
+        }
+        int rc = build_setup(g[i], c->inst[i].s, err);
+        if (rc) {
+            delete c;
+            return fail(nullptr, rc, "instance " + std::to_string(i) + ": " + err);
+        }
+    }
+    if (!c->dryrun) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+            delete c;
+            return fail(nullptr, TC_EDEVICE, "no HIP device");
+        }
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            delete c;
+            return fail(nullptr, TC_EDEVICE, "cannot query the HIP device");
+        }
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            delete c;
+            return fail(nullptr, TC_EDEVICE, std::string("libtc.so is built for gfx950, device is ") + prop.gcnArchName);
+        }
+        if (hipStreamCreate(&c->own) != hipSuccess) {
+            delete c;
+            return fail(nullptr, TC_EDEVICE, "hipStreamCreate failed");
+        }
+        c->stream = c->own;
+        for (auto& in : c->inst) {
+            int rc = alloc_instance(c, in);
+            if (rc) {
+                std::string m = c->err;
+                for (auto& x : c->inst) free_instance(x);
+                (void)hipStreamDestroy(c->own);
+                delete c;
+                return fail(nullptr, rc, m);
+            }
+        }
+    }
+    *out = c;
+    return TC_OK;
+}
+
+int tc_destroy(tc_ctx* c) {
+    if (!c) return TC_OK;
+    if (!c->dryrun) {
+        (void)hipStreamSynchronize(c->stream);
+        for (auto& in : c->inst) free_instance(in);
+        for (auto& t : c->pending) {
+            if (t.start) (void)hipEventDestroy(t.start);
+            if (t.stop) (void)hipEventDestroy(t.stop);
+        }
+        for (auto e : c->pool) (void)hipEventDestroy(e);
+        if (c->own) (void)hipStreamDestroy(c->own);
+    }
+    delete c;
+    return TC_OK;
+}
+
+int tc_set_stream(tc_ctx* c, void* stream) {
+    if (!c) return TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    collect_timing(c);
+    (void)hipStreamSynchronize(c->stream);
+    c->stream = stream ? static_cast<hipStream_t>(stream) : c->own;
+    return TC_OK;
+}
+
+int tc_mode_shape(const tc_ctx* cc, int inst, int* nr, int* nj, int* nl) {
+    tc_ctx* c = const_cast<tc_ctx*>(cc);
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (nr) *nr = in->s.nr;
+    if (nj) *nj = in->s.nj;
+    if (nl) *nl = in->s.nl;
+    return TC_OK;
+}
+
+int tc_grid(const tc_ctx* cc, int inst, double* r) {
+    tc_ctx* c = const_cast<tc_ctx*>(cc);
+    Instance* in = get_inst(c, inst);
+    if (!in || !r) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
+    std::memcpy(r, in->s.r.data(), in->s.nr * sizeof(double));
+    return TC_OK;
+}
+
+int tc_load_fields(tc_ctx* c, int inst, const double* v, const double* eta, const double* um, const double* wm) {
+    Instance* in = get_inst(c, inst);
+    if (!in || !v || !eta || !um || !wm) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    if (int rc = validate_fields(c, *in, v, eta, um, wm)) return rc;
+    const size_t S = (size_t)in->s.nr * in->g.P;
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(in->b.v, v, S * 16, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(in->b.eta, eta, S * 16, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(in->b.umean, um, in->s.nr * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(in->b.wmean, wm, in->s.nr * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemsetAsync(in->b.nv, 0, S * 16, s));
+    HIPCHK(c, hipMemsetAsync(in->b.neta, 0, S * 16, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    in->time = 0.0;
+    in->steps = 0;
+    return TC_OK;
+}
+
+int tc_get_fields(tc_ctx* c, int inst, double* v, double* eta, double* um, double* wm) {
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    const size_t S = (size_t)in->s.nr * in->g.P;
+    hipStream_t s = c->stream;
+    if (v) HIPCHK(c, hipMemcpyAsync(v, in->b.v, S * 16, hipMemcpyDeviceToHost, s));
+    if (eta) HIPCHK(c, hipMemcpyAsync(eta, in->b.eta, S * 16, hipMemcpyDeviceToHost, s));
+    if (um) HIPCHK(c, hipMemcpyAsync(um, in->b.umean, in->s.nr * 8, hipMemcpyDeviceToHost, s));
+    if (wm) HIPCHK(c, hipMemcpyAsync(wm, in->b.wmean, in->s.nr * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return TC_OK;
+}
+
+static int finite_check(tc_ctx* c) {
+    int bad = 0;
+    for (auto& in : c->inst) {
+        timed(c, K_FINITE, [&] { launch_finite(in.g, in.b, c->stream); });
+        if (int rc = check_launch(c, "finite check")) return rc;
+        double flag = 0.0;
+        HIPCHK(c, hipMemcpyAsync(&flag, in.b.stats + 5, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (flag != 0.0) bad = 1;
+    }
+    return bad ? fail(c, TC_ENONFINITE, "non-finite values in the state") : TC_OK;
+}
+
+int tc_step(tc_ctx* c, int nsteps) {
+    if (!c) return TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    if (nsteps < 0) return fail(c, TC_EINVAL, "nsteps must be >= 0");
+    for (int it = 0; it < nsteps; ++it) {
+        for (int k = 0; k < 3; ++k)
+            if (int rc = run_substep(c, k)) return rc;
+        for (auto& in : c->inst) {
+            in.time += in.s.g.dt;
+            in.steps += 1;
+        }
+    }
+    if (int rc = finite_check(c)) return rc;
+    return TC_OK;
+}
+
+int tc_substep(tc_ctx* c, int k) {
+    if (!c) return TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    if (k < 1 || k > 3) return fail(c, TC_EINVAL, "substep index must be 1, 2 or 3");
+    if (int rc = run_substep(c, k - 1)) return rc;
+    return finite_check(c);
+}
+
+int tc_velocity(tc_ctx* c, int inst, double* u, double* w) {
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    const size_t S = (size_t)in->s.nr * in->g.P;
+    launch_dv(in->g, in->b, c->stream);
+    // rv / re are scratch between substeps
+    launch_velocity(in->g, in->b, in->b.rv, in->b.re, c->stream);
+    if (int rc = check_launch(c, "velocity")) return rc;
+    if (u) HIPCHK(c, hipMemcpyAsync(u, in->b.rv, S * 16, hipMemcpyDeviceToHost, c->stream));
+    if (w) HIPCHK(c, hipMemcpyAsync(w, in->b.re, S * 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TC_OK;
+}
+
+int tc_products(tc_ctx* c, int inst, double* prod) {
+    Instance* in = get_inst(c, inst);
+    if (!in || !prod) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    if (int rc = products_only(c, *in)) return rc;
+    const size_t S = (size_t)in->s.nr * in->g.P;
+    if (c->fp32) {
+        std::vector<float> tmp(12 * S);
+        HIPCHK(c, hipMemcpyAsync(tmp.data(), in->b.ps, 12 * S * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < 12 * S; ++i) prod[i] = tmp[i];
+    } else {
+        HIPCHK(c, hipMemcpyAsync(prod, in->b.ps, 12 * S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return TC_OK;
+}
+
+int tc_stats(tc_ctx* c, int inst, tc_stats_t* out) {
+    Instance* in = get_inst(c, inst);
+    if (!in || !out) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    timed(c, K_DV, [&] { launch_dv(in->g, in->b, c->stream); });
+    timed(c, K_ENERGY, [&] { launch_stats(in->g, in->b, c->stream); });
+    if (int rc = check_launch(c, "stats")) return rc;
+    double st[5];
+    HIPCHK(c, hipMemcpyAsync(st, in->b.stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Setup& s = in->s;
+    double vol = 0.0;
+    for (int n = 0; n < s.nr; ++n) {
+        double w = n == 0 ? 0.5 * (s.r[1] - s.r[0])
+                 : n == s.nr - 1 ? 0.5 * (s.r[n] - s.r[n - 1])
+                 : 0.5 * (s.r[n + 1] - s.r[n - 1]);
+        vol += w * s.r[n];
+    }
+    const double gi = st[0], go = st[1];
+    out->time = in->time;
+    out->torque_in = 2.0 * M_PI * s.ri * gi;
+    out->torque_out = 2.0 * M_PI * s.ro * s.ro * go / s.ri;
+    out->tau_in = s.nu * gi;
+    out->tau_out = s.nu * go;
+    out->retau_in = std::sqrt(out->tau_in) * 0.5 * s.g.gap / s.nu;
+    out->retau_out = std::sqrt(out->tau_out) * 0.5 * s.g.gap / s.nu;
+    out->energy = st[2] / (2.0 * vol);
+    out->energy_pert = st[3] / (2.0 * vol);
+    out->steps = in->steps;
+    out->nonfinite = st[4] != 0.0;
+    return TC_OK;
+}
+
+int tc_timing(tc_ctx* c, int enable) {
+    if (!c) return TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    collect_timing(c);
+    if (enable) {
+        for (int i = 0; i < K_COUNT; ++i) {
+            c->ms[i] = 0.0;
+            c->calls[i] = 0;
+        }
+    }
+    c->timing = enable != 0;
+    return TC_OK;
+}
+
+int tc_kernel_times(tc_ctx* c, double* ms, long long* calls, int n) {
+    if (!c) return TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    collect_timing(c);
+    for (int i = 0; i < n && i < K_COUNT; ++i) {
+        if (ms) ms[i] = c->ms[i];
+        if (calls) calls[i] = c->calls[i];
+    }
+    return TC_OK;
+}
+
+int tc_kernel_count(void) { return K_COUNT; }
+
+const char* tc_kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : ""; }
+
+double tc_kernel_bytes(const tc_ctx* cc, int inst, int id) {
+    tc_ctx* c = const_cast<tc_ctx*>(cc);
+    Instance* in = get_inst(c, inst);
+    if (!in) return 0.0;
+    const double S = (double)in->s.nr * in->s.nj * in->s.nl;  // spectral points
+    const double Q = (double)in->s.nr * in->s.nz * in->s.nj;  // mixed-space points
+    const double t = c->fp32 ? 8.0 : 16.0;                    // complex size on the FFT side
+    switch (id) {
+        case K_DV: return 32.0 * S;                           // read v, write D v
+        case K_ZINV: return 48.0 * S + 3.0 * t * Q;           // read v, eta, D v; write 3 fields
+        case K_THETA: return 3.0 * t * Q + 6.0 * t * Q;       // read 3 fields; write 6 products
+        case K_ZFWD: return 6.0 * t * Q + 6.0 * t * S;        // read 6; write 6 spectra
+        case K_RHS: return 48.0 * S + 6.0 * t * S + 32.0 * S + 32.0 * S + 32.0 * S;
+                    // read v, eta, D v, 6 spectra, N registers; write N registers and RHS
+        case K_SOLVE: return 32.0 * S + 32.0 * S;            // read RHS, write v, eta
+        case K_ENERGY: return 48.0 * S;
+        case K_FINITE: return 32.0 * S;
+    }
+    return 0.0;
+}
+
+int tc_coefficients(const tc_ctx* cc, int inst, double* coef, int* sigma) {
+    tc_ctx* c = const_cast<tc_ctx*>(cc);
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (coef) std::memcpy(coef, in->s.coef.data(), in->s.coef.size() * sizeof(double));
+    if (sigma) std::memcpy(sigma, in->s.sigma.data(), in->s.sigma.size() * sizeof(int));
+    return TC_OK;
+}
+
+const char* tc_last_error(const tc_ctx* c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"

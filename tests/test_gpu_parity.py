@@ -1,0 +1,196 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar (FP64 path): relative L2 <= 1e-12 per field per step, with the Hermitian
+weights of the stored half spectrum; statistics to the same relative bar.
+Fields compared: v, eta, u (mean included), w (mean included), w' (mean
+excluded) and the mean profiles.
+"""
+
+import numpy as np
+import pytest
+
+from paper_0711_1429_amd import tc as tcb
+from tests.helpers import pair, rel_l2, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _compare_state(orc, gpu, tol=TOL, label=""):
+    v, e, um, wm = gpu.get_fields()
+    rv, re_, rum, rwm = orc.fields()
+    errs = {"v": rel_l2(v, rv), "eta": rel_l2(e, re_)}
+    errs["w_mean"] = rel_l2(wm, rwm)
+    if np.linalg.norm(rum) > 0:
+        errs["u_mean"] = rel_l2(um, rum)
+    else:
+        errs["u_mean_abs"] = float(np.max(np.abs(um)))
+    gu, gw = gpu.velocity()
+    dv, u, w, c = orc.velocity()
+    shape = v.shape
+    u = u.reshape(shape)
+    w = w.reshape(shape)
+    errs["u"] = rel_l2(gu, u)
+    errs["w"] = rel_l2(gw, w)
+    kz = (shape[2] - 1) // 2
+    wp, gwp = w.copy(), gw.copy()
+    wp[:, 0, kz] = 0
+    gwp[:, 0, kz] = 0
+    errs["w_pert"] = rel_l2(gwp, wp)
+    bad = {k: x for k, x in errs.items() if not x <= tol}
+    print(label, {k: f"{x:.2e}" for k, x in errs.items()}, flush=True)
+    assert not bad, (label, bad)
+    return errs
+
+
+def test_velocity_and_products_small():
+    orc, gpu = pair(workload("tc-small-fp64"))
+    _compare_state(orc, gpu, label="loaded")
+    dv, u, w, c = orc.velocity()
+    P = orc.products(u, orc.v, w)
+    G = gpu.products()
+    for k in P:
+        ref = P[k].reshape(G[k].shape)
+        err = rel_l2(G[k], ref)
+        print(k, f"{err:.2e}", flush=True)
+        assert err < 1e-13, (k, err)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_single_substep_small(k):
+    orc, gpu = pair(workload("tc-small-fp64"))
+    # advance both by the earlier substeps so that substep k sees non-zero
+    # explicit-term registers
+    for kk in range(1, k):
+        orc.substep(kk - 1)
+        gpu.substep(kk)
+    orc.substep(k - 1)
+    gpu.substep(k)
+    _compare_state(orc, gpu, label=f"substep {k}")
+
+
+def test_ten_steps_small_every_step():
+    w = workload("tc-small-fp64")
+    orc, gpu = pair(w)
+    for s in range(w["steps"]):
+        orc.step(1)
+        gpu.step(1)
+        _compare_state(orc, gpu, label=f"step {s + 1}")
+    so, sg = orc.stats(), gpu.stats()
+    for key in ("torque_in", "torque_out", "retau_in", "retau_out", "energy", "energy_pert"):
+        assert abs(sg[key] / so[key] - 1) < TOL, (key, sg[key], so[key])
+    assert sg["steps"] == w["steps"] and sg["nonfinite"] == 0
+    assert abs(sg["time"] - so["time"]) < 1e-15
+
+
+def test_medium_grid_three_steps():
+    w = workload("tc-medium-fp64")
+    orc, gpu = pair(w)
+    for s in range(3):
+        orc.step(1)
+        gpu.step(1)
+    _compare_state(orc, gpu, label="medium step 3")
+
+
+@pytest.mark.parametrize("sizes", [dict(nr=7, ntheta=4, nz=4), dict(nr=9, ntheta=48, nz=36, stretch=1.0),
+                                   dict(nr=20, ntheta=12, nz=96), dict(nr=11, ntheta=96, nz=6)])
+def test_ragged_and_degenerate_sizes(sizes):
+    w = workload("tc-small-fp64", amplitude=1e-2, **sizes)
+    orc, gpu = pair(w)
+    for s in range(2):
+        orc.step(1)
+        gpu.step(1)
+    _compare_state(orc, gpu, tol=TOL, label=str(sizes))
+
+
+def test_rotating_outer_wall_and_custom_domain():
+    w = workload("tc-small-fp64", zeta=0.5, re=120.0, re_outer=-30.0, lz=2.0, theta_period=np.pi,
+                 amplitude=1e-2)
+    orc, gpu = pair(w)
+    orc.step(3)
+    gpu.step(3)
+    _compare_state(orc, gpu, label="outer rotation")
+    so, sg = orc.stats(), gpu.stats()
+    assert abs(sg["torque_out"] / so["torque_out"] - 1) < TOL
+
+
+def test_turbulent_size_one_substep_sampled():
+    """Full turbulent-case grid (129 x 768 x 384, tanh clustering), in the
+    launch configuration the benchmark times: one substep on the GPU, checked
+    on a sample of modes the oracle solves one by one (its products still
+    cover the whole grid)."""
+    w = workload("tc-turbulent-fp64")
+    orc, gpu = pair(w)
+    gpu.substep(1)
+    rng = np.random.default_rng(7)
+    nmodes = orc.nmodes
+    sample = rng.choice(np.flatnonzero(~orc.mc.is_mean), size=48, replace=False)
+    j0 = np.flatnonzero((orc.m_flat == 0) & (orc.alpha_flat != 0))[:2]
+    hi = [nmodes - 1, nmodes - 2]
+    sample = np.unique(np.concatenate([sample, j0, hi]))
+    vs, es = orc.substep_sample(0, sample)
+    v, e, um, wm = gpu.get_fields()
+    v = v.reshape(v.shape[0], -1)[:, sample]
+    e = e.reshape(e.shape[0], -1)[:, sample]
+    ev = np.linalg.norm(v - vs) / np.linalg.norm(vs)
+    ee = np.linalg.norm(e - es) / np.linalg.norm(es)
+    print("turbulent sampled", ev, ee, flush=True)
+    assert ev < TOL and ee < TOL
+
+
+def test_loaded_field_validation():
+    w = workload("tc-small-fp64")
+    orc, gpu = pair(w)
+    v, e, um, wm = gpu.get_fields()
+    bad = v.copy()
+    bad[3, 2, 4] = np.nan
+    with pytest.raises(tcb.TcError) as ex:
+        gpu.load_fields(bad, e, um, wm)
+    assert ex.value.code == tcb.TC_ENONFINITE
+    bad = v.copy()
+    bad[0, 1, 1] = 1e-3
+    with pytest.raises(tcb.TcError) as ex:
+        gpu.load_fields(bad, e, um, wm)
+    assert ex.value.code == tcb.TC_ESHAPE
+    bad = v.copy()
+    kz = (v.shape[2] - 1) // 2
+    bad[5, 0, kz + 1] += 1e-3j
+    with pytest.raises(tcb.TcError) as ex:
+        gpu.load_fields(bad, e, um, wm)
+    assert ex.value.code == tcb.TC_ESHAPE
+    wm2 = wm.copy()
+    wm2[0] = 0.9
+    with pytest.raises(tcb.TcError) as ex:
+        gpu.load_fields(v, e, um, wm2)
+    assert ex.value.code == tcb.TC_ESHAPE
+    # the state was left untouched by the failed loads
+    v2 = gpu.get_fields()[0]
+    assert np.array_equal(v, v2)
+
+
+def test_blow_up_is_reported():
+    """A time step far beyond the explicit stability limit makes the state
+    non-finite; the step reports it instead of returning garbage."""
+    w = workload("tc-small-fp64", dt=50.0, amplitude=0.5, re=5000.0)
+    orc, gpu = pair(w)
+    with pytest.raises(tcb.TcError) as ex:
+        gpu.step(40)
+    assert ex.value.code == tcb.TC_ENONFINITE
+    assert gpu.stats()["nonfinite"] == 1
+
+
+def test_deterministic_and_checkpoint_restart():
+    w = workload("tc-medium-fp64")
+    _, a = pair(w)
+    _, b = pair(w)
+    a.step(4)
+    b.step(2)
+    ckpt = b.get_fields()
+    b.load_fields(*ckpt)  # restart from the saved fields at a step boundary
+    # the explicit-term registers are not needed at step boundaries (the
+    # first substep has no N^{k-2} term), so the restarted run is identical
+    b.step(2)
+    fa, fb = a.get_fields(), b.get_fields()
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
