@@ -50,7 +50,11 @@ def statistics(orc, u, w):
     cflat = np.repeat(cj, d.nl)
     dens = (np.abs(u) ** 2 + np.abs(orc.v) ** 2 + np.abs(w) ** 2) * cflat[None, :]
     per_r = dens.sum(axis=1)
-    per_r_pert = per_r - dens[:, orc.mean_index]
+    # the perturbation sum is taken over the other modes directly (subtracting
+    # the O(1) mean-flow term from the total would cancel catastrophically)
+    pert = np.ones(dens.shape[1], dtype=bool)
+    pert[orc.mean_index] = False
+    per_r_pert = dens[:, pert].sum(axis=1)
     wr = trapezoid_weights(r) * r
     vol = wr.sum()
     finite = (np.all(np.isfinite(orc.v)) and np.all(np.isfinite(orc.eta))

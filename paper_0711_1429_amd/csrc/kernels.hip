@@ -610,7 +610,11 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(DevGeom g, DevBuf b, StepCoe
     const int lp = pair - j * (kz + 1);
     const int modeA = j * nl + kz + lp;
     const int modeB = j * nl + kz - lp;
-    const bool two = lp > 0;
+    // On the j = 0 column the -l mode is the complex conjugate of the +l mode
+    // (real fields): only +l is solved and its conjugate is written to -l, so
+    // the stored state stays exactly Hermitian.
+    const bool mirror = (j == 0 && lp > 0);
+    const bool two = lp > 0 && !mirror;
     const bool mean = (j == 0 && lp == 0);
     const int sys = mean ? (eqn == 0 ? SYS_UMEAN : SYS_WMEAN) : (eqn == 0 ? SYS_V : SYS_ETA);
     const double mm = g.m[j], al = g.alpha[kz + lp];
@@ -699,6 +703,7 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(DevGeom g, DevBuf b, StepCoe
             mout[i] = xA.x;
         } else {
             out[(size_t)i * P + modeA] = xA;
+            if (mirror) out[(size_t)i * P + modeB] = cd{xA.x, -xA.y};
         }
         xA2 = xA1;
         xA1 = xA;
@@ -717,7 +722,7 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve(DevGeom g, DevBuf b, StepCoe
     } else {
         out[modeA] = cd{0, 0};
         out[(size_t)(nr - 1) * P + modeA] = cd{0, 0};
-        if (two) {
+        if (two || mirror) {
             out[modeB] = cd{0, 0};
             out[(size_t)(nr - 1) * P + modeB] = cd{0, 0};
         }
