@@ -55,7 +55,10 @@ enum {
 enum { TC_PREC_FP64 = 0, TC_PREC_MIXED = 1 };
 
 enum {
-    TC_FLAG_DRYRUN = 2   /* validate and size only; allocate no device memory */
+    TC_FLAG_DRYRUN = 2,      /* validate and size only; allocate no device memory  */
+    TC_FLAG_GENERIC_FFT = 4  /* use the run-time-length FFT kernels for every size
+                                (the compiled lengths 8..768 otherwise take the
+                                fixed-length kernels); results agree to rounding */
 };
 
 /* Geometry and resolution of one instance (Sec. 2, Fig. 1; Sec. 4).

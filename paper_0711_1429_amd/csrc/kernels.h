@@ -37,6 +37,7 @@ struct DevGeom {
     const float* tw_z_f;
     const double* wr;       // [nr] trapezoid weight * r
     FftPlanDev plan_theta, plan_z;
+    int generic_fft;        // 1: run-time-length FFT kernels even for compiled lengths
 };
 
 // Coefficients of one substep of the low-storage RK3 / Crank--Nicolson scheme.

@@ -25,6 +25,7 @@
 // mixed-precision path); recovery, the radial stages and reductions are FP64.
 #include <cmath>
 
+#include "fft_lane.h"
 #include "kernels.h"
 
 namespace tc {
@@ -851,6 +852,215 @@ __global__ void k_flags_final(DevBuf b, int nblocks) {
     }
 }
 
+// ===================================================== lane-FFT fast path
+// Compile-time transform lengths (see fft_lane.h); the generic kernels above
+// serve every other length.
+
+struct DevSync {
+    __device__ __forceinline__ void operator()() const { __syncthreads(); }
+};
+
+constexpr int zlane_cols(int N) {
+    const int c = 3072 / N;
+    return c < 1 ? 1 : (c > 16 ? 16 : c);
+}
+
+// theta rows: three wavefronts per block, wavefront f owning field f
+// (u, v, w) of W = 64 / TL packed row pairs (z0, z0 + 1).  Each wavefront
+// inverse-transforms its field, the physical fields meet in LDS, and each
+// wavefront then forms and forward-transforms two of the six products.
+template <typename T, int N>
+__global__ __launch_bounds__(192) void k_theta_lane(DevGeom g, const C<T>* __restrict__ zb, C<T>* __restrict__ pb) {
+    using PL = lane::Plan<N>;
+    constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
+    __shared__ C<T> lds[3 * W * N];
+    const int f = threadIdx.x / 64;             // field of this wavefront
+    const int lw = threadIdx.x - f * 64;        // lane within the wavefront
+    const int grp = lw / TL;
+    const int gl = lw - grp * TL;
+    const int rp = blockIdx.x * W + grp;
+    const int nz = g.nz, kt = g.kt, nj = g.nj;
+    const bool active = rp < nz / 2;  // idle groups still reach every barrier
+    const int r = blockIdx.y;
+    const int z0 = 2 * rp;
+    const T* tw = tw_t<T>(g);
+    const DevSync sync;
+    C<T>* mine = lds + (f * W + grp) * N;       // this group's region
+    {
+        C<T> x[P];
+        const C<T>* row0 = zb + (((size_t)f * g.nr + r) * nz + z0) * nj;
+        const C<T>* row1 = row0 + nj;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int p = gl + k * TL;
+            C<T> h = {(T)0, (T)0};
+            if (active) {
+                if (p <= kt) {
+                    C<T> a = row0[p], b = row1[p];
+                    if (p == 0) {
+                        a.y = (T)0;
+                        b.y = (T)0;
+                    }
+                    h = C<T>{a.x - b.y, a.y + b.x};
+                } else if (p >= N - kt) {
+                    const C<T> a = row0[N - p], b = row1[N - p];
+                    h = C<T>{a.x + b.y, b.x - a.y};
+                }
+            }
+            x[k] = h;
+        }
+        lane::fft<T, N, +1, true>(mine, x, gl, tw, sync);
+#pragma unroll
+        for (int s = 0; s < P; ++s) mine[gl + TL * lane::last_slot_to_m<N>(s)] = x[s];
+    }
+    sync();
+    // products owned by wavefront f: (0,0),(0,1) | (0,2),(1,1) | (1,2),(2,2)
+    const int pa = 2 * f, pbi = 2 * f + 1;
+    const int a0 = f == 0 ? 0 : (f == 1 ? 0 : 1), b0 = f == 0 ? 0 : (f == 1 ? 2 : 2);
+    const int a1 = f == 0 ? 0 : (f == 1 ? 1 : 2), b1 = f == 0 ? 1 : (f == 1 ? 1 : 2);
+    const int idx_a = pa == 0 ? 0 : (pa == 2 ? 2 : 4);   // uu, uw, vw
+    const int idx_b = pbi == 1 ? 1 : (pbi == 3 ? 3 : 5); // uv, vv, ww
+    C<T> x0[P], x1[P];
+    {
+        const C<T>* fa0 = lds + (a0 * W + grp) * N;
+        const C<T>* fb0 = lds + (b0 * W + grp) * N;
+        const C<T>* fa1 = lds + (a1 * W + grp) * N;
+        const C<T>* fb1 = lds + (b1 * W + grp) * N;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int p = gl + k * TL;
+            x0[k] = pmul(fa0[p], fb0[p]);
+            x1[k] = pmul(fa1[p], fb1[p]);
+        }
+    }
+    sync();
+#pragma unroll
+    for (int which = 0; which < 2; ++which) {
+        C<T>* x = which == 0 ? x0 : x1;
+        const int prod = which == 0 ? idx_a : idx_b;
+        lane::fft<T, N, -1, false>(mine, x, gl, tw, sync);
+        sync();
+        if (active) {
+            C<T>* out = pb + (((size_t)prod * g.nr + r) * nz + z0) * nj;
+            for (int j = gl; j < nj; j += TL) {
+                const C<T> h = mine[j];
+                const C<T> hm = mine[j == 0 ? 0 : N - j];
+                out[j] = C<T>{(T)0.5 * (h.x + hm.x), (T)0.5 * (h.y - hm.y)};
+                out[nj + j] = C<T>{(T)0.5 * (h.y + hm.y), (T)0.5 * (hm.x - h.x)};
+            }
+        }
+        sync();
+    }
+}
+
+// inverse z transform of u, v, w for JB j-columns of one plane; v, eta and
+// D v are read once per element.
+template <typename T, int N>
+__global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane(
+    DevGeom g, const cd* __restrict__ v, const cd* __restrict__ eta, const cd* __restrict__ dv,
+    const double* __restrict__ umean, const double* __restrict__ wmean, C<T>* __restrict__ zb) {
+    using PL = lane::Plan<N>;
+    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL;
+    __shared__ C<T> lds[JB * N];
+    const int c = threadIdx.x / TL;
+    const int gl = threadIdx.x - c * TL;
+    const int r = blockIdx.y;
+    const int j0 = blockIdx.x * JB;
+    const int nj = g.nj, nl = g.nl, kz = g.kz;
+    const int ncols = min(JB, nj - j0);
+    const int j = j0 + c;
+    const bool active = c < ncols;
+    const double R = g.r[r];
+    const size_t Pm = g.P;
+    const T* tw = tw_z<T>(g);
+    const DevSync sync;
+    C<T> X[3][P];
+    const double mm = active ? g.m[j] : 0.0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int q = gl + k * TL;
+        const int l = q <= kz ? q : q - N;
+        C<T> xu = {(T)0, (T)0}, xv = xu, xw = xu;
+        if (active && l >= -kz) {
+            const size_t e = (size_t)r * Pm + (size_t)j * nl + (l + kz);
+            if (j == 0 && l == 0) {
+                xu.x = (T)umean[r];
+                xw.x = (T)wmean[r];
+            } else {
+                const double al = g.alpha[l + kz];
+                const double a = R * R / (al * al * R * R + mm * mm);
+                const cd vv = v[e];
+                cd u, w;
+                recover(vv, eta[e], dv[e], R, mm, al, a, u, w);
+                xu = C<T>{(T)u.x, (T)u.y};
+                xv = C<T>{(T)vv.x, (T)vv.y};
+                xw = C<T>{(T)w.x, (T)w.y};
+            }
+        }
+        X[0][k] = xu;
+        X[1][k] = xv;
+        X[2][k] = xw;
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        lane::fft<T, N, +1, false>(lds + c * N, X[f], gl, tw, sync);
+        sync();
+        C<T>* out = zb + ((size_t)f * g.nr + r) * N * nj;
+        for (int idx = threadIdx.x; idx < ncols * N; idx += NTH) {
+            const int z = idx / ncols;
+            const int cc = idx - z * ncols;
+            out[(size_t)z * nj + j0 + cc] = lds[cc * N + z];
+        }
+        sync();
+    }
+}
+
+// forward z transform of the six products for JB j-columns of one plane,
+// truncation to |l| <= K_z and normalisation.
+template <typename T, int N>
+__global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane(
+    DevGeom g, const C<T>* __restrict__ pb, C<T>* __restrict__ ps) {
+    using PL = lane::Plan<N>;
+    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL;
+    __shared__ C<T> lds[JB * N];
+    const int c = threadIdx.x / TL;
+    const int gl = threadIdx.x - c * TL;
+    const int r = blockIdx.y;
+    const int j0 = blockIdx.x * JB;
+    const int nj = g.nj, nl = g.nl, kz = g.kz;
+    const int ncols = min(JB, nj - j0);
+    const bool active = c < ncols;
+    const size_t Pm = g.P;
+    const T scale = (T)(1.0 / ((double)g.ntheta * (double)N));
+    const T* tw = tw_z<T>(g);
+    const DevSync sync;
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+        const C<T>* in = pb + ((size_t)f * g.nr + r) * N * nj;
+        for (int idx = threadIdx.x; idx < ncols * N; idx += NTH) {
+            const int z = idx / ncols;
+            const int cc = idx - z * ncols;
+            lds[cc * N + z] = in[(size_t)z * nj + j0 + cc];
+        }
+        sync();
+        C<T> x[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = active ? lds[c * N + gl + k * TL] : C<T>{(T)0, (T)0};
+        sync();
+        lane::fft<T, N, -1, true>(lds + c * N, x, gl, tw, sync);
+        if (active) {
+            C<T>* out = ps + (size_t)f * g.nr * Pm + (size_t)r * Pm + (size_t)(j0 + c) * nl;
+#pragma unroll
+            for (int s = 0; s < P; ++s) {
+                const int q = gl + TL * lane::last_slot_to_m<N>(s);
+                const int l = q <= kz ? q : q - N;
+                if (l >= -kz) out[l + kz] = cscale(x[s], scale);
+            }
+        }
+        sync();
+    }
+}
+
 // Spectral u and w of every mode (mean profiles in the (0,0) slot).
 __global__ __launch_bounds__(NT) void k_velocity(DevGeom g, DevBuf b, cd* __restrict__ uo, cd* __restrict__ wo) {
     const size_t gid = (size_t)blockIdx.x * NT + threadIdx.x;
@@ -895,7 +1105,69 @@ void launch_dv(const DevGeom& g, const DevBuf& b, hipStream_t s) {
     hipLaunchKernelGGL(k_dv, grid, dim3(NT), 0, s, g, b.v, b.dv);
 }
 
+#define TC_LANE_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768)
+
+bool lane_size(int n) {
+    switch (n) {
+#define TC_CASE(N) case N:
+        TC_LANE_SIZES(TC_CASE)
+#undef TC_CASE
+        return true;
+    }
+    return false;
+}
+
+template <typename T, int N>
+void zinv_lane(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    constexpr int JB = zlane_cols(N);
+    dim3 grid((g.nj + JB - 1) / JB, g.nr);
+    hipLaunchKernelGGL((k_zinv_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, g, b.v, b.eta, b.dv,
+                       b.umean, b.wmean, (C<T>*)b.zb);
+}
+template <typename T, int N>
+void zfwd_lane(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    constexpr int JB = zlane_cols(N);
+    dim3 grid((g.nj + JB - 1) / JB, g.nr);
+    hipLaunchKernelGGL((k_zfwd_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, g, (const C<T>*)b.pb,
+                       (C<T>*)b.ps);
+}
+template <typename T, int N>
+void theta_lane(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    constexpr int W = 64 / lane::Plan<N>::TL;
+    dim3 grid((g.nz / 2 + W - 1) / W, g.nr);
+    hipLaunchKernelGGL((k_theta_lane<T, N>), grid, dim3(192), 0, s, g, (const C<T>*)b.zb, (C<T>*)b.pb);
+}
+
+template <typename T>
+bool zinv_fast(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    switch (g.nz) {
+#define TC_CASE(N) case N: zinv_lane<T, N>(g, b, s); return true;
+        TC_LANE_SIZES(TC_CASE)
+#undef TC_CASE
+    }
+    return false;
+}
+template <typename T>
+bool zfwd_fast(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    switch (g.nz) {
+#define TC_CASE(N) case N: zfwd_lane<T, N>(g, b, s); return true;
+        TC_LANE_SIZES(TC_CASE)
+#undef TC_CASE
+    }
+    return false;
+}
+template <typename T>
+bool theta_fast(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    switch (g.ntheta) {
+#define TC_CASE(N) case N: theta_lane<T, N>(g, b, s); return true;
+        TC_LANE_SIZES(TC_CASE)
+#undef TC_CASE
+    }
+    return false;
+}
+
 void launch_zinv(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
+    if (!g.generic_fft && (fp32 ? zinv_fast<float>(g, b, s) : zinv_fast<double>(g, b, s))) return;
     const int jb = zcols_per_block(g.nz, g.nj);
     dim3 grid((g.nj + jb - 1) / jb, g.nr);
     if (fp32) {
@@ -910,6 +1182,7 @@ void launch_zinv(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
 }
 
 void launch_theta(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
+    if (!g.generic_fft && (fp32 ? theta_fast<float>(g, b, s) : theta_fast<double>(g, b, s))) return;
     dim3 grid(g.nz / 2, g.nr);
     if (fp32) {
         size_t lds = (size_t)3 * g.ntheta * sizeof(C<float>);
@@ -921,6 +1194,7 @@ void launch_theta(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
 }
 
 void launch_zfwd(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
+    if (!g.generic_fft && (fp32 ? zfwd_fast<float>(g, b, s) : zfwd_fast<double>(g, b, s))) return;
     const int jb = zcols_per_block(g.nz, g.nj);
     dim3 grid((g.nj + jb - 1) / jb, g.nr);
     if (fp32) {

@@ -167,6 +167,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
         for (int i = 0; i < MAX_RADICES; ++i) d.radix[i] = p.radix[i];
         return d;
     };
+    g.generic_fft = (s.g.flags & TC_FLAG_GENERIC_FFT) ? 1 : 0;
     g.plan_theta = plan(s.plan_theta);
     g.plan_z = plan(s.plan_z);
 

@@ -21,11 +21,11 @@ def oracle_geometry(w):
                     lz=w.get("lz", 0.0), theta_period=w.get("theta_period", 0.0))
 
 
-def abi_geometry(w, precision=tcb.TC_PREC_FP64):
+def abi_geometry(w, precision=tcb.TC_PREC_FP64, flags=0):
     return tcb.make_geometry(zeta=w["zeta"], re=w["re"], nr=w["nr"], ntheta=w["ntheta"], nz=w["nz"],
                              dt=w["dt"], stretch=w.get("stretch", 0.0), re_outer=w.get("re_outer", 0.0),
                              lz=w.get("lz", 0.0), theta_period=w.get("theta_period", 0.0),
-                             precision=precision)
+                             precision=precision, flags=flags)
 
 
 def fields_for(w, r):
@@ -33,10 +33,10 @@ def fields_for(w, r):
                           w_outer=w.get("re_outer", 0.0) / w["re"])
 
 
-def pair(w, precision=tcb.TC_PREC_FP64):
+def pair(w, precision=tcb.TC_PREC_FP64, flags=0):
     """(oracle, gpu solver) loaded with the same seeded fields."""
     orc = Oracle(oracle_geometry(w))
-    gpu = tcb.Solver(abi_geometry(w, precision))
+    gpu = tcb.Solver(abi_geometry(w, precision, flags))
     flds = fields_for(w, orc.disc.r)
     orc.load(*flds)
     gpu.load_fields(*flds)

@@ -15,6 +15,9 @@ from tests.helpers import pair, rel_l2, workload
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
+# both transform paths: the fixed-length lane kernels (default for the
+# compiled lengths) and the run-time-length kernels
+PATHS = pytest.mark.parametrize("flags", [0, tcb.TC_FLAG_GENERIC_FFT], ids=["lane-fft", "generic-fft"])
 
 
 def _compare_state(orc, gpu, tol=TOL, label=""):
@@ -43,8 +46,9 @@ def _compare_state(orc, gpu, tol=TOL, label=""):
     return errs
 
 
-def test_velocity_and_products_small():
-    orc, gpu = pair(workload("tc-small-fp64"))
+@PATHS
+def test_velocity_and_products_small(flags):
+    orc, gpu = pair(workload("tc-small-fp64"), flags=flags)
     _compare_state(orc, gpu, label="loaded")
     dv, u, w, c = orc.velocity()
     P = orc.products(u, orc.v, w)
@@ -69,9 +73,10 @@ def test_single_substep_small(k):
     _compare_state(orc, gpu, label=f"substep {k}")
 
 
-def test_ten_steps_small_every_step():
+@PATHS
+def test_ten_steps_small_every_step(flags):
     w = workload("tc-small-fp64")
-    orc, gpu = pair(w)
+    orc, gpu = pair(w, flags=flags)
     for s in range(w["steps"]):
         orc.step(1)
         gpu.step(1)
@@ -83,20 +88,24 @@ def test_ten_steps_small_every_step():
     assert abs(sg["time"] - so["time"]) < 1e-15
 
 
-def test_medium_grid_three_steps():
+@PATHS
+def test_medium_grid_three_steps(flags):
     w = workload("tc-medium-fp64")
-    orc, gpu = pair(w)
+    orc, gpu = pair(w, flags=flags)
     for s in range(3):
         orc.step(1)
         gpu.step(1)
     _compare_state(orc, gpu, label="medium step 3")
 
 
+@PATHS
 @pytest.mark.parametrize("sizes", [dict(nr=7, ntheta=4, nz=4), dict(nr=9, ntheta=48, nz=36, stretch=1.0),
-                                   dict(nr=20, ntheta=12, nz=96), dict(nr=11, ntheta=96, nz=6)])
-def test_ragged_and_degenerate_sizes(sizes):
+                                   dict(nr=20, ntheta=12, nz=96), dict(nr=11, ntheta=96, nz=6),
+                                   dict(nr=13, ntheta=768, nz=8), dict(nr=10, ntheta=24, nz=768),
+                                   dict(nr=12, ntheta=384, nz=64)])
+def test_ragged_and_degenerate_sizes(sizes, flags):
     w = workload("tc-small-fp64", amplitude=1e-2, **sizes)
-    orc, gpu = pair(w)
+    orc, gpu = pair(w, flags=flags)
     for s in range(2):
         orc.step(1)
         gpu.step(1)
@@ -114,13 +123,14 @@ def test_rotating_outer_wall_and_custom_domain():
     assert abs(sg["torque_out"] / so["torque_out"] - 1) < TOL
 
 
-def test_turbulent_size_one_substep_sampled():
+@PATHS
+def test_turbulent_size_one_substep_sampled(flags):
     """Full turbulent-case grid (129 x 768 x 384, tanh clustering), in the
     launch configuration the benchmark times: one substep on the GPU, checked
     on a sample of modes the oracle solves one by one (its products still
     cover the whole grid)."""
     w = workload("tc-turbulent-fp64")
-    orc, gpu = pair(w)
+    orc, gpu = pair(w, flags=flags)
     gpu.substep(1)
     rng = np.random.default_rng(7)
     nmodes = orc.nmodes
@@ -193,3 +203,33 @@ def test_deterministic_and_checkpoint_restart():
     fa, fb = a.get_fields(), b.get_fields()
     for x, y in zip(fa, fb):
         assert np.array_equal(x, y)
+
+
+def test_mixed_precision_small_ten_steps():
+    """Mixed precision (FP32 transforms and products, FP64 radial solves,
+    mean flow and statistics) against the FP64 oracle."""
+    w = workload("tc-small-fp64")
+    orc, gpu = pair(w, precision=tcb.TC_PREC_MIXED)
+    orc.step(w["steps"])
+    gpu.step(w["steps"])
+    errs = _compare_state(orc, gpu, tol=1e-5, label="mixed 10 steps")
+    so, sg = orc.stats(), gpu.stats()
+    assert abs(sg["torque_in"] / so["torque_in"] - 1) < 1e-6
+    assert max(errs.values()) > 1e-12  # the FP32 stages really ran
+
+
+def test_lane_and_generic_paths_agree_at_turbulent_size():
+    """The two transform implementations give the same products on the full
+    turbulent-case grid (to FP64 rounding)."""
+    w = workload("tc-turbulent-fp64")
+    from tests.helpers import abi_geometry, fields_for
+    a = tcb.Solver(abi_geometry(w))
+    b = tcb.Solver(abi_geometry(w, flags=tcb.TC_FLAG_GENERIC_FFT))
+    f = fields_for(w, a.grid())
+    a.load_fields(*f)
+    b.load_fields(*f)
+    pa, pb_ = a.products(), b.products()
+    for k in pa:
+        err = rel_l2(pa[k], pb_[k])
+        print("lane vs generic", k, f"{err:.2e}", flush=True)
+        assert err < 1e-13
