@@ -35,6 +35,9 @@ def parse():
                    help="modes the CPU baseline solves radially (the transforms cover the whole grid)")
     p.add_argument("--copy-calib", action="store_true",
                    help="only run a device copy of known size (counter calibration)")
+    p.add_argument("--accuracy", type=str, default="",
+                   help="comma-separated step counts: run the FP64 and mixed paths side by side "
+                        "and report the mixed path's relative L2 error after those steps")
     return p.parse_args()
 
 
@@ -86,6 +89,49 @@ def cpu_baseline(w, nmodes_sample):
     }
 
 
+def _rel(a, b, cj):
+    return float(np.sqrt(np.sum(cj * np.abs(a - b) ** 2) / np.sum(cj * np.abs(b) ** 2)))
+
+
+def accuracy(w, checkpoints):
+    """Mixed-precision error growth: the FP64 GPU path (which matches the FP64
+    oracle to <= 1e-12 per step in the parity tests) is the reference."""
+    from paper_0711_1429_amd import tc
+    from paper_0711_1429_amd.synth import initial_fields
+    geo = dict(zeta=w["zeta"], re=w["re"], nr=w["nr"], ntheta=w["ntheta"], nz=w["nz"],
+               dt=w["dt"], stretch=w["stretch"])
+    ref = tc.Solver(tc.make_geometry(**geo))
+    mix = tc.Solver(tc.make_geometry(precision=tc.TC_PREC_MIXED, **geo))
+    fields = initial_fields(ref.grid(), w["zeta"], w["ntheta"], w["nz"], w["amplitude"], w["seed"])
+    ref.load_fields(*fields)
+    mix.load_fields(*fields)
+    nj = ref.mode_shape()[1]
+    cj = np.where(np.arange(nj) == 0, 1.0, 2.0)[None, :, None]
+    done = 0
+    out = []
+    for target in checkpoints:
+        ref.step(target - done)
+        mix.step(target - done)
+        done = target
+        v0, e0, u0m, w0m = ref.get_fields()
+        v1, e1, u1m, w1m = mix.get_fields()
+        uu0, ww0 = ref.velocity()
+        uu1, ww1 = mix.velocity()
+        kz = (v0.shape[2] - 1) // 2
+        wp0, wp1 = ww0.copy(), ww1.copy()
+        wp0[:, 0, kz] = 0
+        wp1[:, 0, kz] = 0
+        s0, s1 = ref.stats(), mix.stats()
+        rec = {"steps": target, "v": _rel(v1, v0, cj), "eta": _rel(e1, e0, cj), "u": _rel(uu1, uu0, cj),
+               "w": _rel(ww1, ww0, cj), "w_pert": _rel(wp1, wp0, cj),
+               "torque_in": abs(s1["torque_in"] / s0["torque_in"] - 1),
+               "torque_out": abs(s1["torque_out"] / s0["torque_out"] - 1),
+               "energy_pert": abs(s1["energy_pert"] / s0["energy_pert"] - 1)}
+        print(json.dumps(rec), file=sys.stderr, flush=True)
+        out.append(rec)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -94,6 +140,13 @@ def main():
         sys.exit(2)
     if args.copy_calib:
         copy_calibration()
+        return
+    if args.accuracy:
+        from paper_0711_1429_amd.synth import WORKLOADS
+        w = dict(WORKLOADS[args.workload])
+        cps = sorted(int(x) for x in args.accuracy.split(","))
+        print(json.dumps({"workload": args.workload, "reference": "FP64 GPU path",
+                          "mixed_vs_fp64": accuracy(w, cps)}), flush=True)
         return
     from paper_0711_1429_amd import tc
     from paper_0711_1429_amd.synth import WORKLOADS, initial_fields

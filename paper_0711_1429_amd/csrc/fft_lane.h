@@ -213,26 +213,76 @@ __host__ __device__ constexpr int last_slot_to_m(int slot) {
     return slot / Plan<N>::RLAST + (slot % Plan<N>::RLAST) * Plan<N>::KLAST;
 }
 
+// LDS address of transform element e.  For N >= 64 the low four bits of e
+// are XOR-ed with bits 2..5 (12 points per lane) or 3..6 (8 points per lane):
+// a bijection inside each aligned block of 16 elements that spreads the
+// strided stores of the Stockham passes over distinct LDS banks.
+template <int N>
+__host__ __device__ __forceinline__ int swz(int e) {
+    if constexpr (N >= 64 && N % 16 == 0) {
+        constexpr int S = points_per_lane(N) == 12 ? 2 : 3;
+        return e ^ ((e >> S) & 15);
+    } else {
+        return e;
+    }
+}
+
+// ------------------------------------------------------------------ twiddles
+// Pass p > 0 multiplies element k of butterfly jb by w^(k * (jb mod NS_p) *
+// STEP_p) with w = exp(+-2 pi i / N).  The per-pass table holds
+// w^(jm * STEP_p) for jm < NS_p at offset tw_offset(N, p), so the lanes of a
+// pass read consecutive entries; the powers k = 2.. are formed by
+// multiplication.
+constexpr int tw_offset(int N, int pass) {
+    int off = 0;
+    for (int q = 1; q < pass; ++q) off += ns_before(N, q);
+    return off;
+}
+
+template <int N>
+constexpr int tw_size() { return tw_offset(N, Plan<N>::NPASS); }
+
+// Fill the per-pass table from a full table of exp(+2 pi i e / N) (2N reals).
+template <typename T, int N, int PASS>
+__host__ __device__ __forceinline__ void fill_pass(C<T>* twp, const T* tw_full, int tid, int nthreads) {
+    if constexpr (PASS < Plan<N>::NPASS) {
+        constexpr int NS = ns_before(N, PASS);
+        constexpr int STEP = N / (NS * radices(N).r[PASS]);
+        constexpr int OFF = tw_offset(N, PASS);
+        for (int jm = tid; jm < NS; jm += nthreads) {
+            const int e = jm * STEP;
+            twp[OFF + jm] = C<T>{tw_full[2 * e], tw_full[2 * e + 1]};
+        }
+        fill_pass<T, N, PASS + 1>(twp, tw_full, tid, nthreads);
+    }
+}
+
+template <typename T, int N>
+__host__ __device__ __forceinline__ void fill_twiddles(C<T>* twp, const T* tw_full, int tid, int nthreads) {
+    fill_pass<T, N, 1>(twp, tw_full, tid, nthreads);
+}
+
 // ------------------------------------------------------------------ passes
 template <typename T, int N, int PASS, int SIGN>
-__host__ __device__ __forceinline__ void butterflies(C<T>* x, int g, const T* tw) {
+__host__ __device__ __forceinline__ void butterflies(C<T>* x, int g, const C<T>* twp) {
     constexpr Radices rad = radices(N);
     constexpr int R = rad.r[PASS];
     constexpr int NS = ns_before(N, PASS);
     constexpr int TL = Plan<N>::TL;
     constexpr int K = Plan<N>::P / R;
-    constexpr int STEP = N / (NS * R);
 #pragma unroll
     for (int t = 0; t < K; ++t) {
         if constexpr (NS > 1) {
             const int jb = g + t * TL;
             const int jm = jb % NS;
+            constexpr int OFF = tw_offset(N, PASS);
+            C<T> w1 = twp[OFF + jm];
+            if (SIGN < 0) w1.y = -w1.y;
+            C<T> wk = w1;
 #pragma unroll
             for (int k = 1; k < R; ++k) {
-                const int e = jm * k * STEP;
-                C<T> w = {tw[2 * e], tw[2 * e + 1]};
-                if (SIGN < 0) w.y = -w.y;
-                x[t * R + k] = mul(x[t * R + k], w);
+                x[t * R + k] = mul(x[t * R + k], wk);
+                if (k + 1 < R) wk = mul(wk, w1);
             }
         }
         dft<T, R, SIGN>(x + t * R);
@@ -249,7 +299,7 @@ __host__ __device__ __forceinline__ void load_pass(const C<T>* buf, C<T>* x, int
 #pragma unroll
     for (int t = 0; t < K; ++t)
 #pragma unroll
-        for (int k = 0; k < R; ++k) x[t * R + k] = buf[g + t * TL + k * (N / R)];
+        for (int k = 0; k < R; ++k) x[t * R + k] = buf[swz<N>(g + t * TL + k * (N / R))];
 }
 
 // Write the outputs of pass PASS to the transform's LDS region (natural
@@ -266,16 +316,16 @@ __host__ __device__ __forceinline__ void store_pass(C<T>* buf, const C<T>* x, in
         const int jb = g + t * TL;
         const int idx = (jb / NS) * NS * R + jb % NS;
 #pragma unroll
-        for (int k = 0; k < R; ++k) buf[idx + k * NS] = x[t * R + k];
+        for (int k = 0; k < R; ++k) buf[swz<N>(idx + k * NS)] = x[t * R + k];
     }
 }
 
 // Runs passes PASS.. with x holding the inputs of pass PASS.  When
 // OUT_REGS, the last pass's outputs stay in x (layout above); otherwise they
-// are written to buf in natural order.  SYNC() is called between every LDS
+// are written to buf, element e at swz<N>(e).  SYNC() is called between every LDS
 // write and read (and between a read and the next overwrite of buf).
 template <typename T, int N, int PASS, int SIGN, bool OUT_REGS, typename Sync>
-__host__ __device__ __forceinline__ void run_passes(C<T>* buf, C<T>* x, int g, const T* tw, const Sync& sync) {
+__host__ __device__ __forceinline__ void run_passes(C<T>* buf, C<T>* x, int g, const C<T>* tw, const Sync& sync) {
     constexpr int NP = Plan<N>::NPASS;
     if constexpr (PASS < NP) {
         butterflies<T, N, PASS, SIGN>(x, g, tw);
@@ -291,9 +341,10 @@ __host__ __device__ __forceinline__ void run_passes(C<T>* buf, C<T>* x, int g, c
     }
 }
 
-// Full transform: x[k] holds position g + k * TL on entry.
+// Full transform: x[k] holds position g + k * TL on entry; tw is the per-pass
+// twiddle table filled by fill_twiddles.
 template <typename T, int N, int SIGN, bool OUT_REGS, typename Sync>
-__host__ __device__ __forceinline__ void fft(C<T>* buf, C<T>* x, int g, const T* tw, const Sync& sync) {
+__host__ __device__ __forceinline__ void fft(C<T>* buf, C<T>* x, int g, const C<T>* tw, const Sync& sync) {
     run_passes<T, N, 0, SIGN, OUT_REGS>(buf, x, g, tw, sync);
 }
 

@@ -62,7 +62,9 @@ struct DevBuf {
     void* zb;          // [3][nr][nz][nj]  after the inverse z transform (T)
     void* pb;          // [6][nr][nz][nj]  products after the forward theta transform (T)
     void* ps;          // [6][nr][nj][nl]  product spectra (T)
-    double* fac;       // [2][3][nr][npairs] elimination factors
+    double* lu;        // [3][2][5][nr][npairs] precomputed LU factors per substep
+    double* fold;      // [3][2][2][npairs] boundary-row folding factors
+    double* mwall;     // [3][2][nr] wall terms of the mean-profile right-hand sides
     double* partial;   // reduction partials
     int* flags;        // reduction flags
     double* stats;     // [16] statistics
@@ -88,7 +90,9 @@ void launch_zinv(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
 void launch_theta(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
 void launch_zfwd(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
 void launch_rhs(const DevGeom& g, const DevBuf& b, bool fp32, const StepCoef& c, hipStream_t s);
-void launch_solve(const DevGeom& g, const DevBuf& b, const StepCoef& c, hipStream_t s);
+// precomputed LU factors of substep k (run once per context and k)
+void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, hipStream_t s);
+void launch_solve(const DevGeom& g, const DevBuf& b, int k, hipStream_t s);
 // spectral u, w of the current state (needs b.dv up to date)
 void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>* w, hipStream_t s);
 // energy reductions + finite check + statistics into b.stats

@@ -199,6 +199,10 @@ __device__ __forceinline__ void recover(cd v, cd eta, cd dv, double R, double m,
 }
 
 // ---------------------------------------------------------------- k_dv
+// Rows are processed in chunks of DV_CH whose loads are issued together, so
+// one memory latency is paid per chunk rather than per row.
+constexpr int DV_CH = 8;
+
 __global__ __launch_bounds__(NT) void k_dv(DevGeom g, const cd* __restrict__ v, cd* __restrict__ dv) {
     const int mode = blockIdx.x * NT + threadIdx.x;
     if (mode >= g.P) return;
@@ -219,30 +223,57 @@ __global__ __launch_bounds__(NT) void k_dv(DevGeom g, const cd* __restrict__ v, 
     dv[1 * P + mode] = e1;
     dv[(size_t)(nr - 2) * P + mode] = el;
     dv[(size_t)(nr - 1) * P + mode] = cd{0.0, 0.0};
+    // rolling window w[0..3] = v[n-2 .. n+1]; v[n+2] arrives from the chunk
+    cd w0 = v[0 * P + mode], w1 = v[1 * P + mode], w2 = v[2 * P + mode], w3 = v[3 * P + mode];
     cd y1 = {0.0, 0.0}, y2 = {0.0, 0.0};
-    for (int n = 2; n <= nr - 3; ++n) {
-        cd rhs = {0.0, 0.0};
-        for (int j = 0; j < 5; ++j) {
-            const int col = n - 2 + j;
-            rhs = cfma(d1[n * 5 + j], v[(size_t)col * P + mode], rhs);
-            if (col == 1) rhs = cfma(-d0[n * 5 + j], e1, rhs);
-            if (col == nr - 2) rhs = cfma(-d0[n * 5 + j], el, rhs);
+    for (int n0 = 2; n0 <= nr - 3; n0 += DV_CH) {
+        cd vin[DV_CH];
+#pragma unroll
+        for (int c = 0; c < DV_CH; ++c) {
+            const int m = n0 + c + 2;
+            vin[c] = m <= nr - 1 ? v[(size_t)m * P + mode] : cd{0.0, 0.0};
         }
-        const double* L = g.blu + n * 5;
-        cd y = cfma(-L[0], y2, cfma(-L[1], y1, rhs));
-        dv[(size_t)n * P + mode] = y;
-        y2 = y1;
-        y1 = y;
+#pragma unroll
+        for (int c = 0; c < DV_CH; ++c) {
+            const int n = n0 + c;
+            if (n > nr - 3) break;
+            const cd w4 = vin[c];
+            const double* k1 = d1 + n * 5;
+            const double* k0 = d0 + n * 5;
+            cd rhs = cfma(k1[0], w0, cfma(k1[1], w1, cfma(k1[2], w2, cfma(k1[3], w3, cfma(k1[4], w4, cd{0, 0})))));
+            // known D v at rows 1 and nr-2 move to the right-hand side
+            if (n - 2 <= 1 && n + 2 >= 1) rhs = cfma(-k0[1 - (n - 2)], e1, rhs);
+            if (n - 2 <= nr - 2 && n + 2 >= nr - 2) rhs = cfma(-k0[nr - 2 - (n - 2)], el, rhs);
+            const double* L = g.blu + n * 5;
+            const cd y = cfma(-L[0], y2, cfma(-L[1], y1, rhs));
+            dv[(size_t)n * P + mode] = y;
+            y2 = y1;
+            y1 = y;
+            w0 = w1;
+            w1 = w2;
+            w2 = w3;
+            w3 = w4;
+        }
     }
     cd x1 = {0.0, 0.0}, x2 = {0.0, 0.0};
-    for (int n = nr - 3; n >= 2; --n) {
-        const double* L = g.blu + n * 5;
-        cd y = dv[(size_t)n * P + mode];
-        cd t = cfma(-L[4], x2, cfma(-L[3], x1, y));
-        cd x = {t.x * L[2], t.y * L[2]};
-        dv[(size_t)n * P + mode] = x;
-        x2 = x1;
-        x1 = x;
+    for (int n0 = nr - 3; n0 >= 2; n0 -= DV_CH) {
+        cd yin[DV_CH];
+#pragma unroll
+        for (int c = 0; c < DV_CH; ++c) {
+            const int n = n0 - c;
+            yin[c] = n >= 2 ? dv[(size_t)n * P + mode] : cd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int c = 0; c < DV_CH; ++c) {
+            const int n = n0 - c;
+            if (n < 2) break;
+            const double* L = g.blu + n * 5;
+            const cd t = cfma(-L[4], x2, cfma(-L[3], x1, yin[c]));
+            const cd x = {t.x * L[2], t.y * L[2]};
+            dv[(size_t)n * P + mode] = x;
+            x2 = x1;
+            x1 = x;
+        }
     }
 }
 
@@ -424,126 +455,158 @@ __device__ __forceinline__ cd ldp(const C<TP>* p, size_t i) {
     return cd{(double)x.x, (double)x.y};
 }
 
+// One lane per (mode, chunk of RHS_ROWS consecutive radial rows).  The lane
+// visits every input point of its chunk's stencils once (RHS_ROWS + 4 points
+// for an interior chunk), forms the per-point operands of every compact
+// family once, and scatters them into the accumulators of the rows whose
+// 5-point stencil contains the point.
+constexpr int RHS_ROWS = 8;
+
+// mean (0,0) mode: mean axial and azimuthal momentum, one row
 template <typename TP>
-__global__ __launch_bounds__(NT) void k_rhs(DevGeom g, DevBuf b, const C<TP>* __restrict__ ps, StepCoef sc) {
-    const size_t gid = (size_t)blockIdx.x * NT + threadIdx.x;
+__device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, const C<TP>* __restrict__ ps,
+                                             const StepCoef& sc, int n) {
     const size_t P = g.P;
     const int nr = g.nr;
-    if (gid >= (size_t)nr * P) return;
-    const int n = (int)(gid / P);
-    const int mode = (int)(gid - (size_t)n * P);
+    const int mode = g.mean;
+    const size_t gid = (size_t)n * P + mode;
     const size_t S = (size_t)nr * P;
-    const double* d0 = g.coef + ((size_t)0 * nr + n) * 5;
-    const double* d1 = g.coef + ((size_t)1 * nr + n) * 5;
-    const double* d2 = g.coef + ((size_t)2 * nr + n) * 5;
-    const double* d2s = g.coef + ((size_t)3 * nr + n) * 5;
-    const double* d4s = g.coef + ((size_t)4 * nr + n) * 5;
-    const int s = g.sigma[n];
-    const double bdt = sc.bdt_nu, nu = g.nu;
-
-    if (mode == g.mean) {
-        cd rv = {0.0, 0.0}, re = {0.0, 0.0};
-        if (n >= 1 && n <= nr - 2) {
-            double iu = 0, iw = 0, fu = 0, fw = 0;
-            for (int jj = 0; jj < 5; ++jj) {
-                const int m = s + jj;
-                const double R = g.r[m];
-                const double um = b.umean[m], wm = b.wmean[m];
-                const double uv = (double)ps[1 * S + (size_t)m * P + mode].x;
-                const double vw = (double)ps[4 * S + (size_t)m * P + mode].x;
-                iu += d0[jj] * (um + bdt * um / (R * R)) + d2s[jj] * (bdt * um);
-                iw += d0[jj] * wm + d2s[jj] * (bdt * wm);
-                fu -= d1[jj] * uv + d0[jj] * (uv / R);
-                fw -= d1[jj] * vw + d0[jj] * (2.0 * vw / R);
-            }
-            const double pu = b.nv[gid].x, pw = b.neta[gid].x;
-            rv.x = iu + sc.dt * (sc.gamma * fu + sc.rho * pu);
-            re.x = iw + sc.dt * (sc.gamma * fw + sc.rho * pw);
-            b.nv[gid] = cd{fu, 0.0};
-            b.neta[gid] = cd{fw, 0.0};
+    const double bdt = sc.bdt_nu;
+    cd rv = {0.0, 0.0}, re = {0.0, 0.0};
+    if (n >= 1 && n <= nr - 2) {
+        const int s = g.sigma[n];
+        const double* d0 = g.coef + ((size_t)0 * nr + n) * 5;
+        const double* d1 = g.coef + ((size_t)1 * nr + n) * 5;
+        const double* d2s = g.coef + ((size_t)3 * nr + n) * 5;
+        double iu = 0, iw = 0, fu = 0, fw = 0;
+        for (int jj = 0; jj < 5; ++jj) {
+            const int m = s + jj;
+            const double R = g.r[m];
+            const double um = b.umean[m], wm = b.wmean[m];
+            const double uv = (double)ps[1 * S + (size_t)m * P + mode].x;
+            const double vw = (double)ps[4 * S + (size_t)m * P + mode].x;
+            iu += d0[jj] * (um + bdt * um / (R * R)) + d2s[jj] * (bdt * um);
+            iw += d0[jj] * wm + d2s[jj] * (bdt * wm);
+            fu -= d1[jj] * uv + d0[jj] * (uv / R);
+            fw -= d1[jj] * vw + d0[jj] * (2.0 * vw / R);
         }
-        b.rv[gid] = rv;
-        b.re[gid] = re;
+        const double pu = b.nv[gid].x, pw = b.neta[gid].x;
+        rv.x = iu + sc.dt * (sc.gamma * fu + sc.rho * pu);
+        re.x = iw + sc.dt * (sc.gamma * fw + sc.rho * pw);
+        b.nv[gid] = cd{fu, 0.0};
+        b.neta[gid] = cd{fw, 0.0};
+    }
+    b.rv[gid] = rv;
+    b.re[gid] = re;
+}
+
+template <typename TP>
+__global__ __launch_bounds__(NT) void k_rhs(DevGeom g, DevBuf b, const C<TP>* __restrict__ ps, StepCoef sc) {
+    const size_t gid0 = (size_t)blockIdx.x * NT + threadIdx.x;
+    const size_t P = g.P;
+    const int nr = g.nr;
+    const int nchunk = (nr + RHS_ROWS - 1) / RHS_ROWS;
+    if (gid0 >= (size_t)nchunk * P) return;
+    const int chunk = (int)(gid0 / P);
+    const int mode = (int)(gid0 - (size_t)chunk * P);
+    const int n0 = chunk * RHS_ROWS;
+    const int n1 = min(nr, n0 + RHS_ROWS);
+    if (mode == g.mean) {
+        for (int n = n0; n < n1; ++n) rhs_mean_row<TP>(g, b, ps, sc, n);
         return;
     }
-
+    const size_t S = (size_t)nr * P;
+    const double bdt = sc.bdt_nu, nu = g.nu;
     const int j = mode / g.nl;
     const int li = mode - j * g.nl;
     const double mm = g.m[j], al = g.alpha[li];
-    const bool vrow = n >= 2 && n <= nr - 3;
-    const bool erow = n >= 1 && n <= nr - 2;
-    cd Iv = {0, 0}, Nv = {0, 0}, Ie = {0, 0}, Ne = {0, 0};
-    if (erow) {
-        for (int jj = 0; jj < 5; ++jj) {
-            const size_t e = (size_t)(s + jj) * P + mode;
-            const double R = g.r[s + jj];
-            const cd v = b.v[e], eta = b.eta[e], dv = b.dv[e];
-            const cd UU = ldp(ps, e), UV = ldp(ps, S + e), UW = ldp(ps, 2 * S + e);
-            const cd VV = ldp(ps, 3 * S + e), VW = ldp(ps, 4 * S + e), WW = ldp(ps, 5 * S + e);
-            const Wn wc = wavecoef(mm, al, R);
-            cd u, w;
-            recover(v, eta, dv, R, mm, al, wc.a, u, w);
-            const double iR = 1.0 / R, iR2 = iR * iR, iR3 = iR2 * iR;
-            const cd iu = ci(u), iUV = ci(UV), iVW = ci(VW);
-            // eta equation (eq. (final-eta))
-            Ie = cfma(d0[jj] * (1.0 - bdt * wc.k2), eta, Ie);
-            Ie = cfma(d2s[jj] * bdt, eta, Ie);
-            cd n0 = cfma(4.0 * nu * mm * iR3, iu, cd{0, 0});
-            n0 = cfma(2.0 * nu * mm * al * iR2, v, n0);
-            n0 = cfma(mm * al * iR, UU, n0);
-            n0 = cfma(-2.0 * mm * iR2, iUV, n0);
-            n0 = cfma(mm * mm * iR2 - al * al, UW, n0);
-            n0 = cfma(-al * mm * iR, WW, n0);
-            n0 = cfma(2.0 * al * iR, iVW, n0);
-            cd n1 = cfma(2.0 * nu * mm * iR2, iu, cd{0, 0});
-            n1 = cfma(-mm * iR, iUV, n1);
-            n1 = cfma(al, iVW, n1);
-            Ne = cfma(d0[jj], n0, Ne);
-            Ne = cfma(d1[jj], n1, Ne);
-            if (vrow) {
-                // v equation (eq. (final-v))
-                const cd c = {-al * u.y - mm * iR * w.y, al * u.x + mm * iR * w.x};  // i alpha u + i (m/R) w
-                const cd iw = ci(w);
-                Iv = cfma(d0[jj] * (1.0 - bdt * wc.k2), v, Iv);
-                Iv = cfma(d1[jj] * (wc.a1 + bdt * (wc.a2 * iR + wc.a3 - wc.a1 * iR2 - 2.0 * mm * mm * wc.a * iR3)), v, Iv);
-                Iv = cfma(d2s[jj] * (-wc.a + bdt * (2.0 - 2.0 * wc.a1 * iR)), v, Iv);
-                Iv = cfma(d4s[jj] * (-bdt * wc.a), v, Iv);
-                cd v0 = cfma(-2.0 * nu * mm * iR2, iw, cd{0, 0});
-                v0 = cfma(-al, iUV, v0);
-                v0 = cfma(-mm * iR, iVW, v0);
-                v0 = cfma(-iR, VV, v0);
-                v0 = cfma(iR, WW, v0);
-                cd v1 = cfma(2.0 * nu * mm * (wc.a * iR3 - wc.a1 * iR2), iw, cd{0, 0});
-                v1 = cfma(al * wc.a1, iUV, v1);
-                v1 = cfma(mm * (wc.a1 * iR - 3.0 * wc.a * iR2), iVW, v1);
-                v1 = cfma(wc.a * al * al, UU, v1);
-                v1 = cfma(wc.a * 2.0 * al * mm * iR, UW, v1);
-                v1 = cfma(wc.a * mm * mm * iR2, WW, v1);
-                v1 = cfma(-1.0, VV, v1);
-                cd v2 = cfma(2.0 * nu * mm * wc.a * iR2, iw, cd{0, 0});
-                v2 = cfma(-mm * wc.a * iR, iVW, v2);
-                cd v2s = cfma(-3.0 * nu * wc.a1, c, cd{0, 0});
-                v2s = cfma(-al * wc.a, iUV, v2s);
-                Nv = cfma(d0[jj], v0, Nv);
-                Nv = cfma(d1[jj], v1, Nv);
-                Nv = cfma(d2[jj], v2, Nv);
-                Nv = cfma(d2s[jj], v2s, Nv);
+    const int mlo = g.sigma[n0];
+    const int mhi = g.sigma[n1 - 1] + 4;
+    cd Iv[RHS_ROWS], Nv[RHS_ROWS], Ie[RHS_ROWS], Ne[RHS_ROWS];
+#pragma unroll
+    for (int c = 0; c < RHS_ROWS; ++c) Iv[c] = Nv[c] = Ie[c] = Ne[c] = cd{0, 0};
+#pragma unroll
+    for (int mi = 0; mi < RHS_ROWS + 4; ++mi) {
+        const int m = mlo + mi;
+        if (m > mhi) break;
+        const size_t e = (size_t)m * P + mode;
+        const double R = g.r[m];
+        const cd v = b.v[e], eta = b.eta[e], dv = b.dv[e];
+        const cd UU = ldp(ps, e), UV = ldp(ps, S + e), UW = ldp(ps, 2 * S + e);
+        const cd VV = ldp(ps, 3 * S + e), VW = ldp(ps, 4 * S + e), WW = ldp(ps, 5 * S + e);
+        const Wn wc = wavecoef(mm, al, R);
+        cd u, w;
+        recover(v, eta, dv, R, mm, al, wc.a, u, w);
+        const double iR = 1.0 / R, iR2 = iR * iR, iR3 = iR2 * iR;
+        const cd iu = ci(u), iUV = ci(UV), iVW = ci(VW), iw = ci(w);
+        // eta equation (eq. (final-eta)): implicit d0, d2s; explicit d0, d1
+        const double ke0 = 1.0 - bdt * wc.k2;
+        cd ne0 = cfma(4.0 * nu * mm * iR3, iu, cd{0, 0});
+        ne0 = cfma(2.0 * nu * mm * al * iR2, v, ne0);
+        ne0 = cfma(mm * al * iR, UU, ne0);
+        ne0 = cfma(-2.0 * mm * iR2, iUV, ne0);
+        ne0 = cfma(mm * mm * iR2 - al * al, UW, ne0);
+        ne0 = cfma(-al * mm * iR, WW, ne0);
+        ne0 = cfma(2.0 * al * iR, iVW, ne0);
+        cd ne1 = cfma(2.0 * nu * mm * iR2, iu, cd{0, 0});
+        ne1 = cfma(-mm * iR, iUV, ne1);
+        ne1 = cfma(al, iVW, ne1);
+        // v equation (eq. (final-v)): implicit d0, d1, d2s, d4s; explicit d0, d1, d2, d2s
+        const cd c = {-al * u.y - mm * iR * w.y, al * u.x + mm * iR * w.x};  // i alpha u + i (m/R) w
+        const double k0 = 1.0 - bdt * wc.k2;
+        const double k1 = wc.a1 + bdt * (wc.a2 * iR + wc.a3 - wc.a1 * iR2 - 2.0 * mm * mm * wc.a * iR3);
+        const double k2s = -wc.a + bdt * (2.0 - 2.0 * wc.a1 * iR);
+        const double k4s = -bdt * wc.a;
+        cd nv0 = cfma(-2.0 * nu * mm * iR2, iw, cd{0, 0});
+        nv0 = cfma(-al, iUV, nv0);
+        nv0 = cfma(-mm * iR, iVW, nv0);
+        nv0 = cfma(-iR, VV, nv0);
+        nv0 = cfma(iR, WW, nv0);
+        cd nv1 = cfma(2.0 * nu * mm * (wc.a * iR3 - wc.a1 * iR2), iw, cd{0, 0});
+        nv1 = cfma(al * wc.a1, iUV, nv1);
+        nv1 = cfma(mm * (wc.a1 * iR - 3.0 * wc.a * iR2), iVW, nv1);
+        nv1 = cfma(wc.a * al * al, UU, nv1);
+        nv1 = cfma(wc.a * 2.0 * al * mm * iR, UW, nv1);
+        nv1 = cfma(wc.a * mm * mm * iR2, WW, nv1);
+        nv1 = cfma(-1.0, VV, nv1);
+        cd nv2 = cfma(2.0 * nu * mm * wc.a * iR2, iw, cd{0, 0});
+        nv2 = cfma(-mm * wc.a * iR, iVW, nv2);
+        cd nv2s = cfma(-3.0 * nu * wc.a1, c, cd{0, 0});
+        nv2s = cfma(-al * wc.a, iUV, nv2s);
+#pragma unroll
+        for (int cc = 0; cc < RHS_ROWS; ++cc) {
+            const int n = n0 + cc;
+            if (n >= n1) break;
+            const int jj = m - g.sigma[n];
+            if (jj < 0 || jj > 4) continue;
+            const double* co = g.coef + (size_t)n * 5 + jj;
+            const size_t fs = (size_t)nr * 5;
+            const double c0 = co[0], c1 = co[fs], c2 = co[2 * fs], c2s = co[3 * fs], c4s = co[4 * fs];
+            if (n >= 1 && n <= nr - 2) {
+                Ie[cc] = cfma(c0 * ke0 + c2s * bdt, eta, Ie[cc]);
+                Ne[cc] = cfma(c0, ne0, cfma(c1, ne1, Ne[cc]));
+            }
+            if (n >= 2 && n <= nr - 3) {
+                Iv[cc] = cfma(c0 * k0 + c1 * k1 + c2s * k2s + c4s * k4s, v, Iv[cc]);
+                Nv[cc] = cfma(c0, nv0, cfma(c1, nv1, cfma(c2, nv2, cfma(c2s, nv2s, Nv[cc]))));
             }
         }
     }
-    cd rv = {0, 0}, re = {0, 0};
-    if (vrow) {
-        const cd pv = b.nv[gid];
-        rv = cfma(sc.dt * sc.gamma, Nv, cfma(sc.dt * sc.rho, pv, Iv));
+#pragma unroll
+    for (int cc = 0; cc < RHS_ROWS; ++cc) {
+        const int n = n0 + cc;
+        if (n >= n1) break;
+        const size_t gid = (size_t)n * P + mode;
+        const bool vrow = n >= 2 && n <= nr - 3;
+        const bool erow = n >= 1 && n <= nr - 2;
+        cd rv = {0, 0}, re = {0, 0};
+        if (vrow) rv = cfma(sc.dt * sc.gamma, Nv[cc], cfma(sc.dt * sc.rho, b.nv[gid], Iv[cc]));
+        if (erow) re = cfma(sc.dt * sc.gamma, Ne[cc], cfma(sc.dt * sc.rho, b.neta[gid], Ie[cc]));
+        b.nv[gid] = vrow ? Nv[cc] : cd{0, 0};
+        b.neta[gid] = erow ? Ne[cc] : cd{0, 0};
+        b.rv[gid] = rv;
+        b.re[gid] = re;
     }
-    if (erow) {
-        const cd pe = b.neta[gid];
-        re = cfma(sc.dt * sc.gamma, Ne, cfma(sc.dt * sc.rho, pe, Ie));
-    }
-    b.nv[gid] = vrow ? Nv : cd{0, 0};
-    b.neta[gid] = erow ? Ne : cd{0, 0};
-    b.rv[gid] = rv;
-    b.re[gid] = re;
 }
 
 // ---------------------------------------------------------------- k_solve
@@ -601,132 +664,196 @@ __device__ __forceinline__ void lhs_row(const DevGeom& g, int sys, double mm, do
     }
 }
 
-__global__ __launch_bounds__(SOLVE_NT) void k_solve(DevGeom g, DevBuf b, StepCoef sc) {
+// Rows are read in chunks of SV_CH ahead of the substitutions so that one
+// memory latency is paid per chunk.
+constexpr int SV_CH = 8;
+
+// ------------------------------------------------ precomputed elimination
+// The Crank--Nicolson matrices depend only on the mode pair, the equation and
+// the substep (through beta_k dt nu), not on the state: their unpivoted LU
+// factors are computed once per context.  lu holds, for substep k and
+// equation e, the fields {l2, l1, 1/u0, u1, u2} of every row and pair;
+// fold holds the two boundary-row folding factors.
+__device__ __forceinline__ size_t lu_index(const DevGeom& g, int k, int eqn, int field, int i, int pair) {
+    return ((((size_t)k * 2 + eqn) * 5 + field) * g.nr + i) * g.npairs + pair;
+}
+
+__global__ __launch_bounds__(SOLVE_NT) void k_factor(DevGeom g, DevBuf b, StepCoef sc, int k) {
     const int pair = blockIdx.x * SOLVE_NT + threadIdx.x;
     if (pair >= g.npairs) return;
-    const int eqn = blockIdx.y;  // 0: v (or mean axial), 1: eta (or mean azimuthal)
-    const int nr = g.nr, kz = g.kz, nl = g.nl;
-    const size_t P = g.P;
+    const int eqn = blockIdx.y;
+    const int nr = g.nr, kz = g.kz;
     const int j = pair / (kz + 1);
     const int lp = pair - j * (kz + 1);
-    const int modeA = j * nl + kz + lp;
-    const int modeB = j * nl + kz - lp;
-    // On the j = 0 column the -l mode is the complex conjugate of the +l mode
-    // (real fields): only +l is solved and its conjugate is written to -l, so
-    // the stored state stays exactly Hermitian.
-    const bool mirror = (j == 0 && lp > 0);
-    const bool two = lp > 0 && !mirror;
     const bool mean = (j == 0 && lp == 0);
     const int sys = mean ? (eqn == 0 ? SYS_UMEAN : SYS_WMEAN) : (eqn == 0 ? SYS_V : SYS_ETA);
-    const double mm = g.m[j], al = g.alpha[kz + lp];
     const double q0 = sys == SYS_WMEAN ? 1.0 : 0.0;
     const double qn = sys == SYS_WMEAN ? g.w_outer : 0.0;
-    cd* rhs = eqn == 0 ? b.rv : b.re;
+    const double mm = g.m[j], al = g.alpha[kz + lp];
     const double bdt = sc.bdt_nu;
-    double* fac = b.fac + (size_t)eqn * 3 * nr * g.npairs;
-    const size_t fstride = (size_t)nr * g.npairs;
-
     double id1 = 0, s11 = 0, s21 = 0, id2 = 0, s12 = 0, s22 = 0;
-    cd yA1 = {0, 0}, yA2 = {0, 0}, yB1 = {0, 0}, yB2 = {0, 0};
     double G[7] = {0, 0, 0, 0, 0, 0, 0};
-    cd gA = {0, 0}, gB = {0, 0};
     for (int i = 1; i <= nr - 2; ++i) {
         double E[7], w0, wn;
         lhs_row(g, sys, mm, al, bdt, i, E, w0, wn);
-        cd rA = rhs[(size_t)i * P + modeA];
-        cd rB = two ? rhs[(size_t)i * P + modeB] : cd{0, 0};
-        rA.x -= w0 * q0 + wn * qn;
+        // the known wall values of the mean profiles move to the right-hand side
+        if (mean) b.mwall[((size_t)k * 2 + eqn) * nr + i] = w0 * q0 + wn * qn;
         if (i == 1) {
-            // fold the entry of column 4 with row 2
             double F[7], f0, fn;
             lhs_row(g, sys, mm, al, bdt, 2, F, f0, fn);
-            cd r2A = rhs[(size_t)2 * P + modeA];
-            cd r2B = two ? rhs[(size_t)2 * P + modeB] : cd{0, 0};
-            r2A.x -= f0 * q0 + fn * qn;
             const double f = E[6] / F[5];
             E[3] -= f * F[2];
             E[4] -= f * F[3];
             E[5] -= f * F[4];
             E[6] = 0.0;
-            rA = cfma(-f, r2A, rA);
-            rB = cfma(-f, r2B, rB);
+            b.fold[(((size_t)k * 2 + eqn) * 2 + 0) * g.npairs + pair] = f;
         }
         if (i == nr - 2) {
-            // fold the entry of column nr-5 with the original row nr-3
             const double f = E[0] / G[1];
             E[1] -= f * G[2];
             E[2] -= f * G[3];
             E[3] -= f * G[4];
             E[0] = 0.0;
-            rA = cfma(-f, gA, rA);
-            rB = cfma(-f, gB, rB);
+            b.fold[(((size_t)k * 2 + eqn) * 2 + 1) * g.npairs + pair] = f;
         }
         if (i == nr - 3) {
 #pragma unroll
-            for (int k = 0; k < 7; ++k) G[k] = E[k];
-            gA = rA;
-            gB = rB;
+            for (int q = 0; q < 7; ++q) G[q] = E[q];
         }
+        double l2 = 0.0, l1 = 0.0;
         if (i >= 3) {
-            const double l2 = E[1] * id2;
+            l2 = E[1] * id2;
             E[2] -= l2 * s12;
             E[3] -= l2 * s22;
-            rA = cfma(-l2, yA2, rA);
-            rB = cfma(-l2, yB2, rB);
         }
         if (i >= 2) {
-            const double l1 = E[2] * id1;
+            l1 = E[2] * id1;
             E[3] -= l1 * s11;
             E[4] -= l1 * s21;
-            rA = cfma(-l1, yA1, rA);
-            rB = cfma(-l1, yB1, rB);
         }
         const double id = 1.0 / E[3];
-        fac[0 * fstride + (size_t)i * g.npairs + pair] = id;
-        fac[1 * fstride + (size_t)i * g.npairs + pair] = E[4];
-        fac[2 * fstride + (size_t)i * g.npairs + pair] = E[5];
-        rhs[(size_t)i * P + modeA] = rA;
-        if (two) rhs[(size_t)i * P + modeB] = rB;
-        id2 = id1; s12 = s11; s22 = s21; yA2 = yA1; yB2 = yB1;
-        id1 = id;  s11 = E[4]; s21 = E[5]; yA1 = rA; yB1 = rB;
+        b.lu[lu_index(g, k, eqn, 0, i, pair)] = l2;
+        b.lu[lu_index(g, k, eqn, 1, i, pair)] = l1;
+        b.lu[lu_index(g, k, eqn, 2, i, pair)] = id;
+        b.lu[lu_index(g, k, eqn, 3, i, pair)] = E[4];
+        b.lu[lu_index(g, k, eqn, 4, i, pair)] = E[5];
+        id2 = id1; s12 = s11; s22 = s21;
+        id1 = id;  s11 = E[4]; s21 = E[5];
     }
+}
+
+// Forward and back substitution with the precomputed factors of substep k,
+// one (|l|, j) pair and one equation per lane; the (0,0) pair solves the
+// mean axial (equation 0) and azimuthal (equation 1) profiles.
+__global__ __launch_bounds__(SOLVE_NT) void k_solve_lu(DevGeom g, DevBuf b, int k) {
+    const int pair = blockIdx.x * SOLVE_NT + threadIdx.x;
+    if (pair >= g.npairs) return;
+    const int eqn = blockIdx.y;
+    const int nr = g.nr, kz = g.kz, nl = g.nl;
+    const size_t P = g.P;
+    const int j = pair / (kz + 1);
+    const int lp = pair - j * (kz + 1);
+    const bool mean = (j == 0 && lp == 0);  // mean axial (eqn 0) / azimuthal (eqn 1) profile
+    const double* mwall = b.mwall + ((size_t)k * 2 + eqn) * nr;
+    const int modeA = j * nl + kz + lp;
+    const int modeB = j * nl + kz - lp;
+    const bool mirror = (j == 0 && lp > 0);  // -l is written as the conjugate of +l
+    const bool two = lp > 0 && !mirror;
+    cd* rhs = eqn == 0 ? b.rv : b.re;
     cd* out = eqn == 0 ? b.v : b.eta;
-    double* mout = eqn == 0 ? b.umean : b.wmean;
-    cd xA1 = {0, 0}, xA2 = {0, 0}, xB1 = {0, 0}, xB2 = {0, 0};
-    for (int i = nr - 2; i >= 1; --i) {
-        const double id = fac[0 * fstride + (size_t)i * g.npairs + pair];
-        const double s1 = fac[1 * fstride + (size_t)i * g.npairs + pair];
-        const double s2 = fac[2 * fstride + (size_t)i * g.npairs + pair];
-        const cd yA = rhs[(size_t)i * P + modeA];
-        cd tA = cfma(-s2, xA2, cfma(-s1, xA1, yA));
-        const cd xA = {tA.x * id, tA.y * id};
-        if (mean) {
-            mout[i] = xA.x;
-        } else {
-            out[(size_t)i * P + modeA] = xA;
-            if (mirror) out[(size_t)i * P + modeB] = cd{xA.x, -xA.y};
+    const double ftop = b.fold[(((size_t)k * 2 + eqn) * 2 + 0) * g.npairs + pair];
+    const double fbot = b.fold[(((size_t)k * 2 + eqn) * 2 + 1) * g.npairs + pair];
+    cd yA1 = {0, 0}, yA2 = {0, 0}, yB1 = {0, 0}, yB2 = {0, 0};
+    cd gA = {0, 0}, gB = {0, 0};
+    for (int i0 = 1; i0 <= nr - 2; i0 += SV_CH) {
+        cd rAc[SV_CH], rBc[SV_CH];
+        double l2c[SV_CH], l1c[SV_CH];
+#pragma unroll
+        for (int c = 0; c < SV_CH; ++c) {
+            const int i = i0 + c;
+            const bool ok = i <= nr - 2;
+            rAc[c] = ok ? rhs[(size_t)i * P + modeA] : cd{0, 0};
+            rBc[c] = (ok && two) ? rhs[(size_t)i * P + modeB] : cd{0, 0};
+            l2c[c] = ok ? b.lu[lu_index(g, k, eqn, 0, i, pair)] : 0.0;
+            l1c[c] = ok ? b.lu[lu_index(g, k, eqn, 1, i, pair)] : 0.0;
         }
-        xA2 = xA1;
-        xA1 = xA;
-        if (two) {
-            const cd yB = rhs[(size_t)i * P + modeB];
-            cd tB = cfma(-s2, xB2, cfma(-s1, xB1, yB));
-            const cd xB = {tB.x * id, tB.y * id};
-            out[(size_t)i * P + modeB] = xB;
-            xB2 = xB1;
-            xB1 = xB;
+#pragma unroll
+        for (int c = 0; c < SV_CH; ++c) {
+            const int i = i0 + c;
+            if (i > nr - 2) break;
+            cd rA = rAc[c], rB = rBc[c];
+            if (mean) rA.x -= mwall[i];
+            if (i == nr - 3) {
+                gA = rA;
+                gB = rB;
+            }
+            if (i == 1) {
+                cd r2A = rhs[(size_t)2 * P + modeA];
+                const cd r2B = two ? rhs[(size_t)2 * P + modeB] : cd{0, 0};
+                if (mean) r2A.x -= mwall[2];
+                rA = cfma(-ftop, r2A, rA);
+                rB = cfma(-ftop, r2B, rB);
+            }
+            if (i == nr - 2) {
+                rA = cfma(-fbot, gA, rA);
+                rB = cfma(-fbot, gB, rB);
+            }
+            rA = cfma(-l2c[c], yA2, cfma(-l1c[c], yA1, rA));
+            rB = cfma(-l2c[c], yB2, cfma(-l1c[c], yB1, rB));
+            rhs[(size_t)i * P + modeA] = rA;
+            if (two) rhs[(size_t)i * P + modeB] = rB;
+            yA2 = yA1; yA1 = rA;
+            yB2 = yB1; yB1 = rB;
+        }
+    }
+    cd xA1 = {0, 0}, xA2 = {0, 0}, xB1 = {0, 0}, xB2 = {0, 0};
+    for (int i0 = nr - 2; i0 >= 1; i0 -= SV_CH) {
+        double idc[SV_CH], s1c[SV_CH], s2c[SV_CH];
+        cd yAc[SV_CH], yBc[SV_CH];
+#pragma unroll
+        for (int c = 0; c < SV_CH; ++c) {
+            const int i = i0 - c;
+            const bool ok = i >= 1;
+            idc[c] = ok ? b.lu[lu_index(g, k, eqn, 2, i, pair)] : 0.0;
+            s1c[c] = ok ? b.lu[lu_index(g, k, eqn, 3, i, pair)] : 0.0;
+            s2c[c] = ok ? b.lu[lu_index(g, k, eqn, 4, i, pair)] : 0.0;
+            yAc[c] = ok ? rhs[(size_t)i * P + modeA] : cd{0, 0};
+            yBc[c] = (ok && two) ? rhs[(size_t)i * P + modeB] : cd{0, 0};
+        }
+#pragma unroll
+        for (int c = 0; c < SV_CH; ++c) {
+            const int i = i0 - c;
+            if (i < 1) break;
+            const cd tA = cfma(-s2c[c], xA2, cfma(-s1c[c], xA1, yAc[c]));
+            const cd xA = {tA.x * idc[c], tA.y * idc[c]};
+            if (mean) {
+                (eqn == 0 ? b.umean : b.wmean)[i] = xA.x;
+            } else {
+                out[(size_t)i * P + modeA] = xA;
+                if (mirror) out[(size_t)i * P + modeB] = cd{xA.x, -xA.y};
+            }
+            xA2 = xA1;
+            xA1 = xA;
+            if (two) {
+                const cd tB = cfma(-s2c[c], xB2, cfma(-s1c[c], xB1, yBc[c]));
+                const cd xB = {tB.x * idc[c], tB.y * idc[c]};
+                out[(size_t)i * P + modeB] = xB;
+                xB2 = xB1;
+                xB1 = xB;
+            }
         }
     }
     if (mean) {
-        mout[0] = q0;
-        mout[nr - 1] = qn;
-    } else {
-        out[modeA] = cd{0, 0};
-        out[(size_t)(nr - 1) * P + modeA] = cd{0, 0};
-        if (two || mirror) {
-            out[modeB] = cd{0, 0};
-            out[(size_t)(nr - 1) * P + modeB] = cd{0, 0};
-        }
+        double* mo = eqn == 0 ? b.umean : b.wmean;
+        mo[0] = eqn == 0 ? 0.0 : 1.0;
+        mo[nr - 1] = eqn == 0 ? 0.0 : g.w_outer;
+        return;
+    }
+    out[modeA] = cd{0, 0};
+    out[(size_t)(nr - 1) * P + modeA] = cd{0, 0};
+    if (two || mirror) {
+        out[modeB] = cd{0, 0};
+        out[(size_t)(nr - 1) * P + modeB] = cd{0, 0};
     }
 }
 
@@ -865,6 +992,15 @@ constexpr int zlane_cols(int N) {
     return c < 1 ? 1 : (c > 16 ? 16 : c);
 }
 
+// Column pitch of the z kernels' LDS tiles: the transposes read or write one
+// element per column for consecutive columns, so the pitch is offset from N
+// by 16 / JB elements (16-byte slots), which puts the JB columns of a group of
+// 16 lanes on distinct banks.
+constexpr int zlane_pitch(int N) {
+    const int jb = zlane_cols(N);
+    return N + ((16 % jb) == 0 ? 16 / jb : 1);
+}
+
 // theta rows: three wavefronts per block, wavefront f owning field f
 // (u, v, w) of W = 64 / TL packed row pairs (z0, z0 + 1).  Each wavefront
 // inverse-transforms its field, the physical fields meet in LDS, and each
@@ -886,6 +1022,9 @@ __global__ __launch_bounds__(192) void k_theta_lane(DevGeom g, const C<T>* __res
     const T* tw = tw_t<T>(g);
     const DevSync sync;
     C<T>* mine = lds + (f * W + grp) * N;       // this group's region
+    __shared__ C<T> twl[lane::tw_size<N>() + 1];  // per-pass twiddles in LDS
+    lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, 192);
+    sync();
     {
         C<T> x[P];
         const C<T>* row0 = zb + (((size_t)f * g.nr + r) * nz + z0) * nj;
@@ -909,7 +1048,7 @@ __global__ __launch_bounds__(192) void k_theta_lane(DevGeom g, const C<T>* __res
             }
             x[k] = h;
         }
-        lane::fft<T, N, +1, true>(mine, x, gl, tw, sync);
+        lane::fft<T, N, +1, true>(mine, x, gl, twl, sync);
 #pragma unroll
         for (int s = 0; s < P; ++s) mine[gl + TL * lane::last_slot_to_m<N>(s)] = x[s];
     }
@@ -938,13 +1077,13 @@ __global__ __launch_bounds__(192) void k_theta_lane(DevGeom g, const C<T>* __res
     for (int which = 0; which < 2; ++which) {
         C<T>* x = which == 0 ? x0 : x1;
         const int prod = which == 0 ? idx_a : idx_b;
-        lane::fft<T, N, -1, false>(mine, x, gl, tw, sync);
+        lane::fft<T, N, -1, false>(mine, x, gl, twl, sync);
         sync();
         if (active) {
             C<T>* out = pb + (((size_t)prod * g.nr + r) * nz + z0) * nj;
             for (int j = gl; j < nj; j += TL) {
-                const C<T> h = mine[j];
-                const C<T> hm = mine[j == 0 ? 0 : N - j];
+                const C<T> h = mine[lane::swz<N>(j)];
+                const C<T> hm = mine[lane::swz<N>(j == 0 ? 0 : N - j)];
                 out[j] = C<T>{(T)0.5 * (h.x + hm.x), (T)0.5 * (h.y - hm.y)};
                 out[nj + j] = C<T>{(T)0.5 * (h.y + hm.y), (T)0.5 * (hm.x - h.x)};
             }
@@ -960,8 +1099,8 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     DevGeom g, const cd* __restrict__ v, const cd* __restrict__ eta, const cd* __restrict__ dv,
     const double* __restrict__ umean, const double* __restrict__ wmean, C<T>* __restrict__ zb) {
     using PL = lane::Plan<N>;
-    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL;
-    __shared__ C<T> lds[JB * N];
+    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL, PITCH = zlane_pitch(N);
+    __shared__ C<T> lds[JB * PITCH];
     const int c = threadIdx.x / TL;
     const int gl = threadIdx.x - c * TL;
     const int r = blockIdx.y;
@@ -974,6 +1113,8 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     const size_t Pm = g.P;
     const T* tw = tw_z<T>(g);
     const DevSync sync;
+    __shared__ C<T> twl[lane::tw_size<N>() + 1];
+    lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
     C<T> X[3][P];
     const double mm = active ? g.m[j] : 0.0;
 #pragma unroll
@@ -1003,13 +1144,16 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     }
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        lane::fft<T, N, +1, false>(lds + c * N, X[f], gl, tw, sync);
+        if (f == 0) sync();  // twiddles in place
+        lane::fft<T, N, +1, true>(lds + c * PITCH, X[f], gl, twl, sync);
+#pragma unroll
+        for (int q = 0; q < P; ++q) lds[c * PITCH + gl + TL * lane::last_slot_to_m<N>(q)] = X[f][q];
         sync();
         C<T>* out = zb + ((size_t)f * g.nr + r) * N * nj;
         for (int idx = threadIdx.x; idx < ncols * N; idx += NTH) {
             const int z = idx / ncols;
             const int cc = idx - z * ncols;
-            out[(size_t)z * nj + j0 + cc] = lds[cc * N + z];
+            out[(size_t)z * nj + j0 + cc] = lds[cc * PITCH + z];
         }
         sync();
     }
@@ -1021,8 +1165,8 @@ template <typename T, int N>
 __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane(
     DevGeom g, const C<T>* __restrict__ pb, C<T>* __restrict__ ps) {
     using PL = lane::Plan<N>;
-    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL;
-    __shared__ C<T> lds[JB * N];
+    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL, PITCH = zlane_pitch(N);
+    __shared__ C<T> lds[JB * PITCH];
     const int c = threadIdx.x / TL;
     const int gl = threadIdx.x - c * TL;
     const int r = blockIdx.y;
@@ -1034,20 +1178,38 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
     const T scale = (T)(1.0 / ((double)g.ntheta * (double)N));
     const T* tw = tw_z<T>(g);
     const DevSync sync;
-#pragma unroll 1
-    for (int f = 0; f < 6; ++f) {
+    __shared__ C<T> twl[lane::tw_size<N>() + 1];
+    lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
+    // the next product's tile (P values per lane) is fetched into registers
+    // while the current one is transformed
+    C<T> nxt[P];
+    auto fetch = [&](int f) {
         const C<T>* in = pb + ((size_t)f * g.nr + r) * N * nj;
-        for (int idx = threadIdx.x; idx < ncols * N; idx += NTH) {
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            const int idx = threadIdx.x + e * NTH;
             const int z = idx / ncols;
             const int cc = idx - z * ncols;
-            lds[cc * N + z] = in[(size_t)z * nj + j0 + cc];
+            nxt[e] = idx < ncols * N ? in[(size_t)z * nj + j0 + cc] : C<T>{(T)0, (T)0};
+        }
+    };
+    fetch(0);
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            const int idx = threadIdx.x + e * NTH;
+            const int z = idx / ncols;
+            const int cc = idx - z * ncols;
+            if (idx < ncols * N) lds[cc * PITCH + z] = nxt[e];
         }
         sync();
+        if (f < 5) fetch(f + 1);
         C<T> x[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = active ? lds[c * N + gl + k * TL] : C<T>{(T)0, (T)0};
+        for (int k = 0; k < P; ++k) x[k] = active ? lds[c * PITCH + gl + k * TL] : C<T>{(T)0, (T)0};
         sync();
-        lane::fft<T, N, -1, true>(lds + c * N, x, gl, tw, sync);
+        lane::fft<T, N, -1, true>(lds + c * PITCH, x, gl, twl, sync);
         if (active) {
             C<T>* out = ps + (size_t)f * g.nr * Pm + (size_t)r * Pm + (size_t)(j0 + c) * nl;
 #pragma unroll
@@ -1207,7 +1369,7 @@ void launch_zfwd(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
 }
 
 void launch_rhs(const DevGeom& g, const DevBuf& b, bool fp32, const StepCoef& c, hipStream_t s) {
-    const size_t total = (size_t)g.nr * g.P;
+    const size_t total = (size_t)((g.nr + RHS_ROWS - 1) / RHS_ROWS) * g.P;
     dim3 grid((unsigned)((total + NT - 1) / NT));
     if (fp32)
         hipLaunchKernelGGL(k_rhs<float>, grid, dim3(NT), 0, s, g, b, (const C<float>*)b.ps, c);
@@ -1215,9 +1377,14 @@ void launch_rhs(const DevGeom& g, const DevBuf& b, bool fp32, const StepCoef& c,
         hipLaunchKernelGGL(k_rhs<double>, grid, dim3(NT), 0, s, g, b, (const C<double>*)b.ps, c);
 }
 
-void launch_solve(const DevGeom& g, const DevBuf& b, const StepCoef& c, hipStream_t s) {
+void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, hipStream_t s) {
     dim3 grid((g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2);
-    hipLaunchKernelGGL(k_solve, grid, dim3(SOLVE_NT), 0, s, g, b, c);
+    hipLaunchKernelGGL(k_factor, grid, dim3(SOLVE_NT), 0, s, g, b, c, k);
+}
+
+void launch_solve(const DevGeom& g, const DevBuf& b, int k, hipStream_t s) {
+    dim3 grid((g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2);
+    hipLaunchKernelGGL(k_solve_lu, grid, dim3(SOLVE_NT), 0, s, g, b, k);
 }
 
 void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>* w, hipStream_t s) {

@@ -123,6 +123,15 @@ int check_launch(tc_ctx* c, const char* what) {
     return TC_OK;
 }
 
+StepCoef step_coef(const Instance& in, int k) {
+    StepCoef sc;
+    sc.dt = in.s.g.dt;
+    sc.gamma = kGamma[k];
+    sc.rho = kRho[k];
+    sc.bdt_nu = 0.5 * (kGamma[k] + kRho[k]) * sc.dt * in.s.nu;
+    return sc;
+}
+
 template <typename T>
 int dev_alloc(tc_ctx* c, Instance& in, T** p, size_t count) {
     void* q = nullptr;
@@ -209,7 +218,9 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     b.pb = raw;
     if ((rc = dev_alloc(c, in, &raw, 6 * S * cz))) return rc;
     b.ps = raw;
-    if ((rc = dev_alloc(c, in, &b.fac, (size_t)2 * 3 * s.nr * g.npairs))) return rc;
+    if ((rc = dev_alloc(c, in, &b.lu, (size_t)3 * 2 * 5 * s.nr * g.npairs))) return rc;
+    if ((rc = dev_alloc(c, in, &b.fold, (size_t)3 * 2 * 2 * g.npairs))) return rc;
+    if ((rc = dev_alloc(c, in, &b.mwall, (size_t)3 * 2 * s.nr))) return rc;
     in.red_blocks = reduction_blocks(g);
     b.partial_n = in.red_blocks;
     if ((rc = dev_alloc(c, in, &b.partial, (size_t)2 * in.red_blocks))) return rc;
@@ -218,6 +229,12 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     for (auto p : c128) HIPCHK(c, hipMemset(*p, 0, S * sizeof(C<double>)));
     HIPCHK(c, hipMemset(b.umean, 0, s.nr * sizeof(double)));
     HIPCHK(c, hipMemset(b.wmean, 0, s.nr * sizeof(double)));
+    HIPCHK(c, hipMemset(b.lu, 0, (size_t)3 * 2 * 5 * s.nr * g.npairs * sizeof(double)));
+    HIPCHK(c, hipMemset(b.fold, 0, (size_t)3 * 2 * 2 * g.npairs * sizeof(double)));
+    HIPCHK(c, hipMemset(b.mwall, 0, (size_t)3 * 2 * s.nr * sizeof(double)));
+    for (int k = 0; k < 3; ++k) launch_factor(g, b, step_coef(in, k), k, c->stream);
+    if (int e = check_launch(c, "factor launch")) return e;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return TC_OK;
 }
 
@@ -238,11 +255,7 @@ int need_device(tc_ctx* c) {
 
 int run_substep(tc_ctx* c, int k) {
     for (auto& in : c->inst) {
-        StepCoef sc;
-        sc.dt = in.s.g.dt;
-        sc.gamma = kGamma[k];
-        sc.rho = kRho[k];
-        sc.bdt_nu = 0.5 * (kGamma[k] + kRho[k]) * sc.dt * in.s.nu;
+        const StepCoef sc = step_coef(in, k);
         const DevGeom& g = in.g;
         const DevBuf& b = in.b;
         hipStream_t s = c->stream;
@@ -251,7 +264,7 @@ int run_substep(tc_ctx* c, int k) {
         timed(c, K_THETA, [&] { launch_theta(g, b, c->fp32, s); });
         timed(c, K_ZFWD, [&] { launch_zfwd(g, b, c->fp32, s); });
         timed(c, K_RHS, [&] { launch_rhs(g, b, c->fp32, sc, s); });
-        timed(c, K_SOLVE, [&] { launch_solve(g, b, sc, s); });
+        timed(c, K_SOLVE, [&] { launch_solve(g, b, k, s); });
     }
     return check_launch(c, "substep launch");
 }
@@ -583,7 +596,8 @@ double tc_kernel_bytes(const tc_ctx* cc, int inst, int id) {
         case K_ZFWD: return 6.0 * t * Q + 6.0 * t * S;        // read 6; write 6 spectra
         case K_RHS: return 48.0 * S + 6.0 * t * S + 32.0 * S + 32.0 * S + 32.0 * S;
                     // read v, eta, D v, 6 spectra, N registers; write N registers and RHS
-        case K_SOLVE: return 32.0 * S + 32.0 * S;            // read RHS, write v, eta
+        case K_SOLVE:  // read RHS and the 5 LU fields of both equations, write v, eta
+            return 32.0 * S + 80.0 * in->s.nr * in->s.nj * (in->s.kz + 1.0) + 32.0 * S;
         case K_ENERGY: return 48.0 * S;
         case K_FINITE: return 32.0 * S;
     }

@@ -32,6 +32,8 @@ double run_case(unsigned seed) {
     std::mt19937_64 rng(seed);
     std::normal_distribution<double> nd;
     for (auto& z : in) z = {nd(rng), nd(rng)};
+    std::vector<C<double>> twp(lane::tw_size<N>() + 1);
+    lane::fill_twiddles<double, N>(twp.data(), tw.data(), 0, 1);
     std::barrier<> bar(P::TL);
     HostSync sync{&bar};
     std::vector<std::thread> th;
@@ -39,13 +41,14 @@ double run_case(unsigned seed) {
         th.emplace_back([&, g] {
             C<double> x[P::P];
             for (int k = 0; k < P::P; ++k) x[k] = in[g + k * P::TL];
-            lane::fft<double, N, SIGN, OUT_REGS>(buf.data(), x, g, tw.data(), sync);
+            lane::fft<double, N, SIGN, OUT_REGS>(buf.data(), x, g, twp.data(), sync);
             if (OUT_REGS)
                 for (int s = 0; s < P::P; ++s) out[g + P::TL * lane::last_slot_to_m<N>(s)] = x[s];
         });
     }
     for (auto& t : th) t.join();
-    if (!OUT_REGS) out = buf;
+    if (!OUT_REGS)
+        for (int k = 0; k < N; ++k) out[k] = buf[lane::swz<N>(k)];
     double err = 0, scale = 0;
     for (int k = 0; k < N; ++k) {
         std::complex<long double> s = 0;
