@@ -179,6 +179,13 @@ int tc_products(tc_ctx* ctx, int inst, double* prod);
 /* Statistics of instance `inst` (FP64 device reductions, fixed order). */
 int tc_stats(tc_ctx* ctx, int inst, tc_stats_t* out);
 
+/* Replay whole steps from a captured HIP graph (enable = 1, the default) or
+ * launch every kernel eagerly (0).  The graph holds one full step of every
+ * instance and is captured on the first tc_step call on a stream; it is
+ * dropped when the stream changes.  Steps taken while per-kernel timing is on
+ * are always launched eagerly. */
+int tc_use_graphs(tc_ctx* ctx, int enable);
+
 /* Per-kernel timing with HIP events on the context's stream.
  * enable = 1 starts recording (and clears the totals), 0 stops.  While on,
  * every launch is bracketed by events; tc_kernel_times fills ms[i] with the

@@ -24,7 +24,7 @@ struct DevGeom {
     int P;            // nj * nl modes per radial plane
     int mean;         // index of the (0,0) mode within a plane (= kz)
     int npairs;       // nj * (kz + 1)
-    double nu, w_outer;
+    double nu, w_outer, dt;
     const double* r;        // [nr]
     const int* sigma;       // [nr]
     const double* coef;     // [5][nr][5]
@@ -40,20 +40,20 @@ struct DevGeom {
     int generic_fft;        // 1: run-time-length FFT kernels even for compiled lengths
 };
 
-// Coefficients of one substep of the low-storage RK3 / Crank--Nicolson scheme.
+// Coefficients of one substep of the low-storage RK3 / Crank--Nicolson
+// scheme (the time step and viscosity are per instance, in DevGeom).
 struct StepCoef {
-    double dt;       // time step
     double gamma;    // weight of N^{k-1}
     double rho;      // weight of N^{k-2}
-    double bdt_nu;   // beta_k dt nu
+    double beta;     // Crank--Nicolson weight
 };
 
 // Device buffers of one instance.  c128 arrays are [nr][nj][nl].
 struct DevBuf {
     C<double>* v;
     C<double>* eta;
-    C<double>* nv;     // explicit-term register of v (mean slot: mean axial)
-    C<double>* neta;   // explicit-term register of eta (mean slot: mean azimuthal)
+    C<double>* nv[2];    // explicit-term registers of v, alternating by substep (mean slot: mean axial)
+    C<double>* neta[2];  // the same for eta (mean slot: mean azimuthal)
     C<double>* dv;     // radial derivative of v
     C<double>* rv;     // right-hand side / forward-elimination values of v
     C<double>* re;     // the same for eta
@@ -71,6 +71,22 @@ struct DevBuf {
     int partial_n;     // capacity of partial (doubles) / flags (ints)
 };
 
+// One instance's tables and buffers, as the batched kernels read them from
+// device memory (blockIdx.z selects the instance).
+struct InstDev {
+    DevGeom g;
+    DevBuf b;
+};
+
+// Instances that share (N_r, N_theta, N_z) and the transform path run in one
+// launch per kernel: inst points to `count` consecutive InstDev in device
+// memory; g is a host copy of any member's tables (launch shapes only).
+struct Batch {
+    const InstDev* inst;
+    int count;
+    DevGeom g;
+};
+
 enum KernelId {
     K_DV = 0,
     K_ZINV,
@@ -85,14 +101,14 @@ enum KernelId {
 
 extern const char* const kKernelNames[K_COUNT];
 
-void launch_dv(const DevGeom& g, const DevBuf& b, hipStream_t s);
-void launch_zinv(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
-void launch_theta(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
-void launch_zfwd(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s);
-void launch_rhs(const DevGeom& g, const DevBuf& b, bool fp32, const StepCoef& c, hipStream_t s);
+void launch_dv(const Batch& B, hipStream_t s);
+void launch_zinv(const Batch& B, bool fp32, hipStream_t s);
+void launch_theta(const Batch& B, bool fp32, hipStream_t s);
+void launch_zfwd(const Batch& B, bool fp32, hipStream_t s);
+void launch_rhs(const Batch& B, bool fp32, const StepCoef& c, int k, hipStream_t s);
 // precomputed LU factors of substep k (run once per context and k)
 void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, hipStream_t s);
-void launch_solve(const DevGeom& g, const DevBuf& b, int k, hipStream_t s);
+void launch_solve(const Batch& B, int k, hipStream_t s);
 // spectral u, w of the current state (needs b.dv up to date)
 void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>* w, hipStream_t s);
 // energy reductions + finite check + statistics into b.stats

@@ -203,7 +203,11 @@ __device__ __forceinline__ void recover(cd v, cd eta, cd dv, double R, double m,
 // one memory latency is paid per chunk rather than per row.
 constexpr int DV_CH = 8;
 
-__global__ __launch_bounds__(NT) void k_dv(DevGeom g, const cd* __restrict__ v, cd* __restrict__ dv) {
+__global__ __launch_bounds__(NT) void k_dv(const InstDev* __restrict__ I) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const cd* __restrict__ v = b.v;
+    cd* __restrict__ dv = b.dv;
     const int mode = blockIdx.x * NT + threadIdx.x;
     if (mode >= g.P) return;
     const int nr = g.nr;
@@ -279,9 +283,15 @@ __global__ __launch_bounds__(NT) void k_dv(DevGeom g, const cd* __restrict__ v, 
 
 // ---------------------------------------------------------------- k_zinv
 template <typename T>
-__global__ __launch_bounds__(NT) void k_zinv(DevGeom g, const cd* __restrict__ v, const cd* __restrict__ eta,
-                                             const cd* __restrict__ dv, const double* __restrict__ umean,
-                                             const double* __restrict__ wmean, C<T>* __restrict__ zb, int jb) {
+__global__ __launch_bounds__(NT) void k_zinv(const InstDev* __restrict__ I, int jb) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const cd* __restrict__ v = b.v;
+    const cd* __restrict__ eta = b.eta;
+    const cd* __restrict__ dv = b.dv;
+    const double* __restrict__ umean = b.umean;
+    const double* __restrict__ wmean = b.wmean;
+    C<T>* __restrict__ zb = (C<T>*)b.zb;
     extern __shared__ __align__(16) char smem_raw[];
     C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
     const int r = blockIdx.y;
@@ -351,7 +361,11 @@ __device__ __forceinline__ void theta_write(const DevGeom& g, const C<T>* buf, C
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_theta(DevGeom g, const C<T>* __restrict__ zb, C<T>* __restrict__ pb) {
+__global__ __launch_bounds__(NT) void k_theta(const InstDev* __restrict__ I) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const C<T>* __restrict__ zb = (const C<T>*)b.zb;
+    C<T>* __restrict__ pb = (C<T>*)b.pb;
     extern __shared__ __align__(16) char smem_raw[];
     C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
     const int r = blockIdx.y;
@@ -417,7 +431,11 @@ __global__ __launch_bounds__(NT) void k_theta(DevGeom g, const C<T>* __restrict_
 
 // ---------------------------------------------------------------- k_zfwd
 template <typename T>
-__global__ __launch_bounds__(NT) void k_zfwd(DevGeom g, const C<T>* __restrict__ pb, C<T>* __restrict__ ps, int jb) {
+__global__ __launch_bounds__(NT) void k_zfwd(const InstDev* __restrict__ I, int jb) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const C<T>* __restrict__ pb = (const C<T>*)b.pb;
+    C<T>* __restrict__ ps = (C<T>*)b.ps;
     extern __shared__ __align__(16) char smem_raw[];
     C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
     const int r = blockIdx.y;
@@ -455,15 +473,31 @@ __device__ __forceinline__ cd ldp(const C<TP>* p, size_t i) {
     return cd{(double)x.x, (double)x.y};
 }
 
-// One lane per (mode, chunk of RHS_ROWS consecutive radial rows).  The lane
-// visits every input point of its chunk's stencils once (RHS_ROWS + 4 points
-// for an interior chunk), forms the per-point operands of every compact
-// family once, and scatters them into the accumulators of the rows whose
-// 5-point stencil contains the point.
-constexpr int RHS_ROWS = 8;
+// One lane per (mode, chunk of rr consecutive rows of 2..nr-3, the rows
+// whose 5-point stencils are centred).  The lane walks the chunk's rr + 4
+// stencil points in increasing r, forms the per-point operands of every
+// compact family once, and scatters them into the accumulators of the five
+// rows whose stencil contains the point.  Row cc of the chunk lives in
+// accumulator slot cc mod 5: its first point assigns the slot, its fifth
+// finishes it and the row is written at once, so five rows of accumulators
+// are live.  The point loop is unrolled by the slot period only (rr + 4 is a
+// multiple of 5), which keeps the kernel small enough for the instruction
+// cache; slots of rows outside the chunk collect values that are never
+// written.  Every chunk is full length: the last one is shifted down to end at
+// row nr-3 and may recompute rows of its neighbour, writing bit-identical
+// values (the kernel reads nothing it writes).  The first chunk also writes
+// the off-centre eta row 1 and the zero row 0, the last chunk the eta row
+// nr-2 and the zero row nr-1.  Lanes are laid out chunk-major over the mode
+// count rounded up to whole wavefronts, so the chunk is wave-uniform and
+// coefficient and grid reads are scalar.
+//
+// The explicit-term registers N alternate between two buffers: substep 0
+// writes n[0] (its rho is zero, so nothing is read), substep 1 reads n[0]
+// and writes n[1], substep 2 reads n[1] and writes nothing (the next
+// substep 0 does not read it).
 
 // mean (0,0) mode: mean axial and azimuthal momentum, one row
-template <typename TP>
+template <typename TP, int K>
 __device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, const C<TP>* __restrict__ ps,
                                              const StepCoef& sc, int n) {
     const size_t P = g.P;
@@ -471,8 +505,9 @@ __device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, 
     const int mode = g.mean;
     const size_t gid = (size_t)n * P + mode;
     const size_t S = (size_t)nr * P;
-    const double bdt = sc.bdt_nu;
+    const double bdt = sc.beta * g.dt * g.nu;
     cd rv = {0.0, 0.0}, re = {0.0, 0.0};
+    cd fnu = {0.0, 0.0}, fnw = {0.0, 0.0};
     if (n >= 1 && n <= nr - 2) {
         const int s = g.sigma[n];
         const double* d0 = g.coef + ((size_t)0 * nr + n) * 5;
@@ -490,123 +525,285 @@ __device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, 
             fu -= d1[jj] * uv + d0[jj] * (uv / R);
             fw -= d1[jj] * vw + d0[jj] * (2.0 * vw / R);
         }
-        const double pu = b.nv[gid].x, pw = b.neta[gid].x;
-        rv.x = iu + sc.dt * (sc.gamma * fu + sc.rho * pu);
-        re.x = iw + sc.dt * (sc.gamma * fw + sc.rho * pw);
-        b.nv[gid] = cd{fu, 0.0};
-        b.neta[gid] = cd{fw, 0.0};
+        double pu = 0.0, pw = 0.0;
+        if (K > 0) {
+            pu = b.nv[K - 1][gid].x;
+            pw = b.neta[K - 1][gid].x;
+        }
+        rv.x = iu + g.dt * (sc.gamma * fu + sc.rho * pu);
+        re.x = iw + g.dt * (sc.gamma * fw + sc.rho * pw);
+        fnu.x = fu;
+        fnw.x = fw;
+    }
+    if (K < 2) {
+        b.nv[K][gid] = fnu;
+        b.neta[K][gid] = fnw;
     }
     b.rv[gid] = rv;
     b.re[gid] = re;
 }
 
 template <typename TP>
-__global__ __launch_bounds__(NT) void k_rhs(DevGeom g, DevBuf b, const C<TP>* __restrict__ ps, StepCoef sc) {
-    const size_t gid0 = (size_t)blockIdx.x * NT + threadIdx.x;
-    const size_t P = g.P;
-    const int nr = g.nr;
-    const int nchunk = (nr + RHS_ROWS - 1) / RHS_ROWS;
-    if (gid0 >= (size_t)nchunk * P) return;
-    const int chunk = (int)(gid0 / P);
-    const int mode = (int)(gid0 - (size_t)chunk * P);
-    const int n0 = chunk * RHS_ROWS;
-    const int n1 = min(nr, n0 + RHS_ROWS);
-    if (mode == g.mean) {
-        for (int n = n0; n < n1; ++n) rhs_mean_row<TP>(g, b, ps, sc, n);
-        return;
+struct RhsPoint {
+    cd v, eta, dv;
+    C<TP> UU, UV, UW, VV, VW, WW;
+};
+
+template <typename TP>
+__device__ __forceinline__ void rhs_load(const cd* __restrict__ v, const cd* __restrict__ eta,
+                                         const cd* __restrict__ dv, const C<TP>* __restrict__ ps, size_t S, size_t e,
+                                         RhsPoint<TP>& p) {
+    p.v = v[e];
+    p.eta = eta[e];
+    p.dv = dv[e];
+    p.UU = ps[e];
+    p.UV = ps[S + e];
+    p.UW = ps[2 * S + e];
+    p.VV = ps[3 * S + e];
+    p.VW = ps[4 * S + e];
+    p.WW = ps[5 * S + e];
+}
+
+// per-point operands of eq. (final-v) and eq. (final-eta): the weights of
+// each compact family in the explicit half of the Crank--Nicolson operator,
+// and the nonlinear-plus-explicit-viscous vectors multiplied by d0, d1, d2, d2s
+struct RhsOps {
+    cd v, eta, ne0, ne1, nv0, nv1, nv2, nv2s;
+    double ke0, kv0, kv1, kv2s, kv4s;
+};
+
+template <typename TP>
+__device__ __forceinline__ RhsOps rhs_ops(const RhsPoint<TP>& p, double R, double mm, double al, double nu,
+                                          double bdt) {
+    const cd UU = {(double)p.UU.x, (double)p.UU.y}, UV = {(double)p.UV.x, (double)p.UV.y};
+    const cd UW = {(double)p.UW.x, (double)p.UW.y}, VV = {(double)p.VV.x, (double)p.VV.y};
+    const cd VW = {(double)p.VW.x, (double)p.VW.y}, WW = {(double)p.WW.x, (double)p.WW.y};
+    const Wn wc = wavecoef(mm, al, R);
+    cd u, w;
+    recover(p.v, p.eta, p.dv, R, mm, al, wc.a, u, w);
+    const double iR = 1.0 / R, iR2 = iR * iR, iR3 = iR2 * iR;
+    const cd iu = ci(u), iUV = ci(UV), iVW = ci(VW), iw = ci(w);
+    RhsOps o;
+    o.v = p.v;
+    o.eta = p.eta;
+    // eta equation (eq. (final-eta)): implicit d0, d2s; explicit d0, d1
+    o.ke0 = 1.0 - bdt * wc.k2;
+    cd ne0 = cfma(4.0 * nu * mm * iR3, iu, cd{0, 0});
+    ne0 = cfma(2.0 * nu * mm * al * iR2, p.v, ne0);
+    ne0 = cfma(mm * al * iR, UU, ne0);
+    ne0 = cfma(-2.0 * mm * iR2, iUV, ne0);
+    ne0 = cfma(mm * mm * iR2 - al * al, UW, ne0);
+    ne0 = cfma(-al * mm * iR, WW, ne0);
+    o.ne0 = cfma(2.0 * al * iR, iVW, ne0);
+    cd ne1 = cfma(2.0 * nu * mm * iR2, iu, cd{0, 0});
+    ne1 = cfma(-mm * iR, iUV, ne1);
+    o.ne1 = cfma(al, iVW, ne1);
+    // v equation (eq. (final-v)): implicit d0, d1, d2s, d4s; explicit d0, d1, d2, d2s
+    const cd c = {-al * u.y - mm * iR * w.y, al * u.x + mm * iR * w.x};  // i alpha u + i (m/R) w
+    o.kv0 = 1.0 - bdt * wc.k2;
+    o.kv1 = wc.a1 + bdt * (wc.a2 * iR + wc.a3 - wc.a1 * iR2 - 2.0 * mm * mm * wc.a * iR3);
+    o.kv2s = -wc.a + bdt * (2.0 - 2.0 * wc.a1 * iR);
+    o.kv4s = -bdt * wc.a;
+    cd nv0 = cfma(-2.0 * nu * mm * iR2, iw, cd{0, 0});
+    nv0 = cfma(-al, iUV, nv0);
+    nv0 = cfma(-mm * iR, iVW, nv0);
+    nv0 = cfma(-iR, VV, nv0);
+    o.nv0 = cfma(iR, WW, nv0);
+    cd nv1 = cfma(2.0 * nu * mm * (wc.a * iR3 - wc.a1 * iR2), iw, cd{0, 0});
+    nv1 = cfma(al * wc.a1, iUV, nv1);
+    nv1 = cfma(mm * (wc.a1 * iR - 3.0 * wc.a * iR2), iVW, nv1);
+    nv1 = cfma(wc.a * al * al, UU, nv1);
+    nv1 = cfma(wc.a * 2.0 * al * mm * iR, UW, nv1);
+    nv1 = cfma(wc.a * mm * mm * iR2, WW, nv1);
+    o.nv1 = cfma(-1.0, VV, nv1);
+    cd nv2 = cfma(2.0 * nu * mm * wc.a * iR2, iw, cd{0, 0});
+    o.nv2 = cfma(-mm * wc.a * iR, iVW, nv2);
+    cd nv2s = cfma(-3.0 * nu * wc.a1, c, cd{0, 0});
+    o.nv2s = cfma(-al * wc.a, iUV, nv2s);
+    return o;
+}
+
+struct RhsAcc {
+    cd Iv, Nv, Ie, Ne;
+};
+
+// eta row: co points at the coefficient of stencil point jj of the row
+__device__ __forceinline__ void rhs_acc_eta(RhsAcc& A, const RhsOps& o, const double* co, size_t fs, double bdt) {
+    const double c0 = co[0], c1 = co[fs], c2s = co[3 * fs];
+    A.Ie = cfma(c0 * o.ke0 + c2s * bdt, o.eta, A.Ie);
+    A.Ne = cfma(c0, o.ne0, cfma(c1, o.ne1, A.Ne));
+}
+
+__device__ __forceinline__ void rhs_acc_both(RhsAcc& A, const RhsOps& o, const double* co, size_t fs, double bdt) {
+    const double c0 = co[0], c1 = co[fs], c2 = co[2 * fs], c2s = co[3 * fs], c4s = co[4 * fs];
+    A.Ie = cfma(c0 * o.ke0 + c2s * bdt, o.eta, A.Ie);
+    A.Ne = cfma(c0, o.ne0, cfma(c1, o.ne1, A.Ne));
+    A.Iv = cfma(c0 * o.kv0 + c1 * o.kv1 + c2s * o.kv2s + c4s * o.kv4s, o.v, A.Iv);
+    A.Nv = cfma(c0, o.nv0, cfma(c1, o.nv1, cfma(c2, o.nv2, cfma(c2s, o.nv2s, A.Nv))));
+}
+
+// right-hand side of one row: (M + beta dt nu L) q + dt (gamma N + rho N_prev)
+template <int K>
+__device__ __forceinline__ void rhs_store(cd* __restrict__ nv, cd* __restrict__ ne, cd* __restrict__ rv,
+                                          cd* __restrict__ re, size_t gid, bool vrow, const RhsAcc& A, cd pv,
+                                          cd pe, double dt, const StepCoef& sc) {
+    cd r = {0, 0};
+    if (vrow) r = cfma(dt * sc.gamma, A.Nv, K > 0 ? cfma(dt * sc.rho, pv, A.Iv) : A.Iv);
+    const cd q = cfma(dt * sc.gamma, A.Ne, K > 0 ? cfma(dt * sc.rho, pe, A.Ie) : A.Ie);
+    if (K < 2) {
+        nv[gid] = vrow ? A.Nv : cd{0, 0};
+        ne[gid] = A.Ne;
     }
+    rv[gid] = r;
+    re[gid] = q;
+}
+
+template <int K>
+__device__ __forceinline__ void rhs_zero_row(cd* __restrict__ nv, cd* __restrict__ ne, cd* __restrict__ rv,
+                                             cd* __restrict__ re, size_t gid) {
+    if (K < 2) {
+        nv[gid] = cd{0, 0};
+        ne[gid] = cd{0, 0};
+    }
+    rv[gid] = cd{0, 0};
+    re[gid] = cd{0, 0};
+}
+
+// An empty asm statement that takes the accumulators as read-write register
+// operands: it pins each accumulation where it is written.  Without it the
+// compiler sinks the accumulations towards the (later, sometimes
+// conditional) stores and keeps several stencil points' operands live
+// instead of one row's accumulator.
+__device__ __forceinline__ void pin_eta(RhsAcc& A) {
+    asm volatile("" : "+v"(A.Ie.x), "+v"(A.Ie.y), "+v"(A.Ne.x), "+v"(A.Ne.y));
+}
+__device__ __forceinline__ void pin_both(RhsAcc& A) {
+    asm volatile("" : "+v"(A.Ie.x), "+v"(A.Ie.y), "+v"(A.Ne.x), "+v"(A.Ne.y), "+v"(A.Iv.x), "+v"(A.Iv.y),
+                 "+v"(A.Nv.x), "+v"(A.Nv.y));
+}
+
+// The lane body.  All pointers are restrict-qualified arguments, so loads of
+// the next stencil point may be scheduled above the stores of finished rows;
+// a scheduling barrier closes every point, so the compiler neither hoists
+// further loads nor interleaves points (either would take the register count
+// above two waves per SIMD).
+template <typename TP, int K>
+__device__ __forceinline__ void rhs_lane(const cd* __restrict__ v, const cd* __restrict__ eta,
+                                         const cd* __restrict__ dv, const C<TP>* __restrict__ ps,
+                                         const cd* __restrict__ pnv, const cd* __restrict__ pne,
+                                         cd* __restrict__ nnv, cd* __restrict__ nne, cd* __restrict__ rv,
+                                         cd* __restrict__ re, const double* __restrict__ coef,
+                                         const double* __restrict__ r, int nr, int P, int mode, int n0, int rr,
+                                         bool first, bool last, double mm, double al, double nu, double dt,
+                                         const StepCoef& sc) {
     const size_t S = (size_t)nr * P;
-    const double bdt = sc.bdt_nu, nu = g.nu;
-    const int j = mode / g.nl;
-    const int li = mode - j * g.nl;
-    const double mm = g.m[j], al = g.alpha[li];
-    const int mlo = g.sigma[n0];
-    const int mhi = g.sigma[n1 - 1] + 4;
-    cd Iv[RHS_ROWS], Nv[RHS_ROWS], Ie[RHS_ROWS], Ne[RHS_ROWS];
+    const size_t fs = (size_t)nr * 5;
+    const double bdt = sc.beta * dt * nu;
+    const int T = rr + 4;  // points, a multiple of 5
+    RhsAcc A[5];
 #pragma unroll
-    for (int c = 0; c < RHS_ROWS; ++c) Iv[c] = Nv[c] = Ie[c] = Ne[c] = cd{0, 0};
+    for (int q = 0; q < 5; ++q) A[q] = RhsAcc{{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    RhsAcc W1 = {{0, 0}, {0, 0}, {0, 0}, {0, 0}}, W2 = W1;  // eta rows 1 and nr-2
+    RhsPoint<TP> nxt;
+    rhs_load<TP>(v, eta, dv, ps, S, (size_t)(n0 - 2) * P + mode, nxt);
+    cd pv = {0, 0}, pe = {0, 0};
+    for (int base = 0; base < T; base += 5) {
 #pragma unroll
-    for (int mi = 0; mi < RHS_ROWS + 4; ++mi) {
-        const int m = mlo + mi;
-        if (m > mhi) break;
-        const size_t e = (size_t)m * P + mode;
-        const double R = g.r[m];
-        const cd v = b.v[e], eta = b.eta[e], dv = b.dv[e];
-        const cd UU = ldp(ps, e), UV = ldp(ps, S + e), UW = ldp(ps, 2 * S + e);
-        const cd VV = ldp(ps, 3 * S + e), VW = ldp(ps, 4 * S + e), WW = ldp(ps, 5 * S + e);
-        const Wn wc = wavecoef(mm, al, R);
-        cd u, w;
-        recover(v, eta, dv, R, mm, al, wc.a, u, w);
-        const double iR = 1.0 / R, iR2 = iR * iR, iR3 = iR2 * iR;
-        const cd iu = ci(u), iUV = ci(UV), iVW = ci(VW), iw = ci(w);
-        // eta equation (eq. (final-eta)): implicit d0, d2s; explicit d0, d1
-        const double ke0 = 1.0 - bdt * wc.k2;
-        cd ne0 = cfma(4.0 * nu * mm * iR3, iu, cd{0, 0});
-        ne0 = cfma(2.0 * nu * mm * al * iR2, v, ne0);
-        ne0 = cfma(mm * al * iR, UU, ne0);
-        ne0 = cfma(-2.0 * mm * iR2, iUV, ne0);
-        ne0 = cfma(mm * mm * iR2 - al * al, UW, ne0);
-        ne0 = cfma(-al * mm * iR, WW, ne0);
-        ne0 = cfma(2.0 * al * iR, iVW, ne0);
-        cd ne1 = cfma(2.0 * nu * mm * iR2, iu, cd{0, 0});
-        ne1 = cfma(-mm * iR, iUV, ne1);
-        ne1 = cfma(al, iVW, ne1);
-        // v equation (eq. (final-v)): implicit d0, d1, d2s, d4s; explicit d0, d1, d2, d2s
-        const cd c = {-al * u.y - mm * iR * w.y, al * u.x + mm * iR * w.x};  // i alpha u + i (m/R) w
-        const double k0 = 1.0 - bdt * wc.k2;
-        const double k1 = wc.a1 + bdt * (wc.a2 * iR + wc.a3 - wc.a1 * iR2 - 2.0 * mm * mm * wc.a * iR3);
-        const double k2s = -wc.a + bdt * (2.0 - 2.0 * wc.a1 * iR);
-        const double k4s = -bdt * wc.a;
-        cd nv0 = cfma(-2.0 * nu * mm * iR2, iw, cd{0, 0});
-        nv0 = cfma(-al, iUV, nv0);
-        nv0 = cfma(-mm * iR, iVW, nv0);
-        nv0 = cfma(-iR, VV, nv0);
-        nv0 = cfma(iR, WW, nv0);
-        cd nv1 = cfma(2.0 * nu * mm * (wc.a * iR3 - wc.a1 * iR2), iw, cd{0, 0});
-        nv1 = cfma(al * wc.a1, iUV, nv1);
-        nv1 = cfma(mm * (wc.a1 * iR - 3.0 * wc.a * iR2), iVW, nv1);
-        nv1 = cfma(wc.a * al * al, UU, nv1);
-        nv1 = cfma(wc.a * 2.0 * al * mm * iR, UW, nv1);
-        nv1 = cfma(wc.a * mm * mm * iR2, WW, nv1);
-        nv1 = cfma(-1.0, VV, nv1);
-        cd nv2 = cfma(2.0 * nu * mm * wc.a * iR2, iw, cd{0, 0});
-        nv2 = cfma(-mm * wc.a * iR, iVW, nv2);
-        cd nv2s = cfma(-3.0 * nu * wc.a1, c, cd{0, 0});
-        nv2s = cfma(-al * wc.a, iUV, nv2s);
-#pragma unroll
-        for (int cc = 0; cc < RHS_ROWS; ++cc) {
-            const int n = n0 + cc;
-            if (n >= n1) break;
-            const int jj = m - g.sigma[n];
-            if (jj < 0 || jj > 4) continue;
-            const double* co = g.coef + (size_t)n * 5 + jj;
-            const size_t fs = (size_t)nr * 5;
-            const double c0 = co[0], c1 = co[fs], c2 = co[2 * fs], c2s = co[3 * fs], c4s = co[4 * fs];
-            if (n >= 1 && n <= nr - 2) {
-                Ie[cc] = cfma(c0 * ke0 + c2s * bdt, eta, Ie[cc]);
-                Ne[cc] = cfma(c0, ne0, cfma(c1, ne1, Ne[cc]));
+        for (int q = 0; q < 5; ++q) {
+            const int mi = base + q;
+            const int m = n0 - 2 + mi;  // <= n0 + rr + 1 <= nr - 1
+            const RhsPoint<TP> cur = nxt;
+            rhs_load<TP>(v, eta, dv, ps, S, (size_t)min(m + 1, nr - 1) * P + mode, nxt);
+            // N_prev of the row finished at the next point (clamped row
+            // index: the first three points read a row that is not used)
+            cd npv = {0, 0}, npe = {0, 0};
+            if (K > 0) {
+                const size_t gid = (size_t)max(n0 + mi - 3, 0) * P + mode;
+                npv = pnv[gid];
+                npe = pne[gid];
             }
-            if (n >= 2 && n <= nr - 3) {
-                Iv[cc] = cfma(c0 * k0 + c1 * k1 + c2s * k2s + c4s * k4s, v, Iv[cc]);
-                Nv[cc] = cfma(c0, nv0, cfma(c1, nv1, cfma(c2, nv2, cfma(c2s, nv2s, Nv[cc]))));
+            const RhsOps o = rhs_ops<TP>(cur, r[m], mm, al, nu, bdt);
+#pragma unroll
+            for (int jj = 0; jj < 5; ++jj) {
+                // row cc = mi - jj in slot (q - jj) mod 5; coefficient rows
+                // of rows outside the chunk are clamped into the table
+                const int slot = (q - jj + 5) % 5;
+                const int n = min(max(n0 + mi - jj, 0), nr - 1);
+                if (jj == 0) A[slot] = RhsAcc{{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+                rhs_acc_both(A[slot], o, coef + (size_t)n * 5 + jj, fs, bdt);
+                pin_both(A[slot]);
             }
+            if (base == 0) {  // sigma_1 = 0: points 0..4 of the first chunk
+                rhs_acc_eta(W1, o, coef + 1 * 5 + q, fs, bdt);
+                pin_eta(W1);
+            }
+            if (base == T - 5) {  // sigma_{nr-2} = nr - 5: the last five points of the last chunk
+                rhs_acc_eta(W2, o, coef + (size_t)(nr - 2) * 5 + q, fs, bdt);
+                pin_eta(W2);
+            }
+            if (q == 4 || base > 0)  // row mi - 4 is complete
+                rhs_store<K>(nnv, nne, rv, re, (size_t)(n0 + mi - 4) * P + mode, true, A[(q + 1) % 5], pv, pe, dt,
+                             sc);
+            pv = npv;
+            pe = npe;
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
-#pragma unroll
-    for (int cc = 0; cc < RHS_ROWS; ++cc) {
-        const int n = n0 + cc;
-        if (n >= n1) break;
-        const size_t gid = (size_t)n * P + mode;
-        const bool vrow = n >= 2 && n <= nr - 3;
-        const bool erow = n >= 1 && n <= nr - 2;
-        cd rv = {0, 0}, re = {0, 0};
-        if (vrow) rv = cfma(sc.dt * sc.gamma, Nv[cc], cfma(sc.dt * sc.rho, b.nv[gid], Iv[cc]));
-        if (erow) re = cfma(sc.dt * sc.gamma, Ne[cc], cfma(sc.dt * sc.rho, b.neta[gid], Ie[cc]));
-        b.nv[gid] = vrow ? Nv[cc] : cd{0, 0};
-        b.neta[gid] = erow ? Ne[cc] : cd{0, 0};
-        b.rv[gid] = rv;
-        b.re[gid] = re;
+    if (first) {
+        cd p1 = {0, 0};
+        if (K > 0) p1 = pne[(size_t)P + mode];
+        rhs_store<K>(nnv, nne, rv, re, (size_t)P + mode, false, W1, cd{0, 0}, p1, dt, sc);
+        rhs_zero_row<K>(nnv, nne, rv, re, (size_t)mode);
     }
+    if (last) {
+        cd p2 = {0, 0};
+        if (K > 0) p2 = pne[(size_t)(nr - 2) * P + mode];
+        rhs_store<K>(nnv, nne, rv, re, (size_t)(nr - 2) * P + mode, false, W2, cd{0, 0}, p2, dt, sc);
+        rhs_zero_row<K>(nnv, nne, rv, re, (size_t)(nr - 1) * P + mode);
+    }
+}
+
+// rows per chunk: rr + 4 must be a multiple of 5 and rr <= nr - 4; the
+// longest such chunk up to RHS_MAX_ROWS
+constexpr int RHS_MAX_ROWS = 21;
+inline int rhs_rows(int nr) {
+    const int cap = min(nr - 4, RHS_MAX_ROWS);
+    return cap - ((cap - 1) % 5);
+}
+
+template <typename TP, int K>
+__global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepCoef sc, int rr) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const C<TP>* __restrict__ ps = (const C<TP>*)b.ps;
+    const int P = g.P;
+    const int Pp = (P + 63) & ~63;
+    const int nr = g.nr;
+    const int nchunk = (nr - 4 + rr - 1) / rr;
+    const int gid0 = blockIdx.x * NT + threadIdx.x;
+    const int chunk = __builtin_amdgcn_readfirstlane(gid0 / Pp);
+    const int mode = gid0 - chunk * Pp;
+    if (chunk >= nchunk || mode >= P) return;
+    const int n0 = min(2 + chunk * rr, nr - 2 - rr);
+    const bool first = chunk == 0, last = chunk == nchunk - 1;
+    if (mode == g.mean) {
+        if (first) {
+            rhs_mean_row<TP, K>(g, b, ps, sc, 0);
+            rhs_mean_row<TP, K>(g, b, ps, sc, 1);
+        }
+        for (int n = n0; n < n0 + rr; ++n) rhs_mean_row<TP, K>(g, b, ps, sc, n);
+        if (last) {
+            rhs_mean_row<TP, K>(g, b, ps, sc, nr - 2);
+            rhs_mean_row<TP, K>(g, b, ps, sc, nr - 1);
+        }
+        return;
+    }
+    const int j = mode / g.nl;
+    const int li = mode - j * g.nl;
+    rhs_lane<TP, K>(b.v, b.eta, b.dv, ps, K > 0 ? b.nv[K > 0 ? K - 1 : 0] : nullptr,
+                    K > 0 ? b.neta[K > 0 ? K - 1 : 0] : nullptr, K < 2 ? b.nv[K < 2 ? K : 0] : nullptr,
+                    K < 2 ? b.neta[K < 2 ? K : 0] : nullptr, b.rv, b.re, g.coef, g.r, nr, P, mode, n0, rr, first,
+                    last, g.m[j], g.alpha[li], g.nu, g.dt, sc);
 }
 
 // ---------------------------------------------------------------- k_solve
@@ -690,7 +887,7 @@ __global__ __launch_bounds__(SOLVE_NT) void k_factor(DevGeom g, DevBuf b, StepCo
     const double q0 = sys == SYS_WMEAN ? 1.0 : 0.0;
     const double qn = sys == SYS_WMEAN ? g.w_outer : 0.0;
     const double mm = g.m[j], al = g.alpha[kz + lp];
-    const double bdt = sc.bdt_nu;
+    const double bdt = sc.beta * g.dt * g.nu;
     double id1 = 0, s11 = 0, s21 = 0, id2 = 0, s12 = 0, s22 = 0;
     double G[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int i = 1; i <= nr - 2; ++i) {
@@ -745,7 +942,9 @@ __global__ __launch_bounds__(SOLVE_NT) void k_factor(DevGeom g, DevBuf b, StepCo
 // Forward and back substitution with the precomputed factors of substep k,
 // one (|l|, j) pair and one equation per lane; the (0,0) pair solves the
 // mean axial (equation 0) and azimuthal (equation 1) profiles.
-__global__ __launch_bounds__(SOLVE_NT) void k_solve_lu(DevGeom g, DevBuf b, int k) {
+__global__ __launch_bounds__(SOLVE_NT) void k_solve_lu(const InstDev* __restrict__ I, int k) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
     const int pair = blockIdx.x * SOLVE_NT + threadIdx.x;
     if (pair >= g.npairs) return;
     const int eqn = blockIdx.y;
@@ -1006,7 +1205,11 @@ constexpr int zlane_pitch(int N) {
 // inverse-transforms its field, the physical fields meet in LDS, and each
 // wavefront then forms and forward-transforms two of the six products.
 template <typename T, int N>
-__global__ __launch_bounds__(192) void k_theta_lane(DevGeom g, const C<T>* __restrict__ zb, C<T>* __restrict__ pb) {
+__global__ __launch_bounds__(192) void k_theta_lane(const InstDev* __restrict__ I) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const C<T>* __restrict__ zb = (const C<T>*)b.zb;
+    C<T>* __restrict__ pb = (C<T>*)b.pb;
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
     __shared__ C<T> lds[3 * W * N];
@@ -1095,9 +1298,15 @@ __global__ __launch_bounds__(192) void k_theta_lane(DevGeom g, const C<T>* __res
 // inverse z transform of u, v, w for JB j-columns of one plane; v, eta and
 // D v are read once per element.
 template <typename T, int N>
-__global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane(
-    DevGeom g, const cd* __restrict__ v, const cd* __restrict__ eta, const cd* __restrict__ dv,
-    const double* __restrict__ umean, const double* __restrict__ wmean, C<T>* __restrict__ zb) {
+__global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane(const InstDev* __restrict__ I) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const cd* __restrict__ v = b.v;
+    const cd* __restrict__ eta = b.eta;
+    const cd* __restrict__ dv = b.dv;
+    const double* __restrict__ umean = b.umean;
+    const double* __restrict__ wmean = b.wmean;
+    C<T>* __restrict__ zb = (C<T>*)b.zb;
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL, PITCH = zlane_pitch(N);
     __shared__ C<T> lds[JB * PITCH];
@@ -1162,8 +1371,11 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
 // forward z transform of the six products for JB j-columns of one plane,
 // truncation to |l| <= K_z and normalisation.
 template <typename T, int N>
-__global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane(
-    DevGeom g, const C<T>* __restrict__ pb, C<T>* __restrict__ ps) {
+__global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane(const InstDev* __restrict__ I) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const C<T>* __restrict__ pb = (const C<T>*)b.pb;
+    C<T>* __restrict__ ps = (C<T>*)b.ps;
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL, PITCH = zlane_pitch(N);
     __shared__ C<T> lds[JB * PITCH];
@@ -1262,119 +1474,109 @@ int reduction_blocks(const DevGeom& g) {
     return (int)nb;
 }
 
-void launch_dv(const DevGeom& g, const DevBuf& b, hipStream_t s) {
-    dim3 grid((g.P + NT - 1) / NT);
-    hipLaunchKernelGGL(k_dv, grid, dim3(NT), 0, s, g, b.v, b.dv);
+void launch_dv(const Batch& B, hipStream_t s) {
+    const DevGeom& g = B.g;
+    dim3 grid((g.P + NT - 1) / NT, 1, B.count);
+    hipLaunchKernelGGL(k_dv, grid, dim3(NT), 0, s, B.inst);
 }
 
 #define TC_LANE_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768)
 
-bool lane_size(int n) {
-    switch (n) {
-#define TC_CASE(N) case N:
-        TC_LANE_SIZES(TC_CASE)
-#undef TC_CASE
-        return true;
-    }
-    return false;
-}
-
 template <typename T, int N>
-void zinv_lane(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+void zinv_lane(const Batch& B, hipStream_t s) {
     constexpr int JB = zlane_cols(N);
-    dim3 grid((g.nj + JB - 1) / JB, g.nr);
-    hipLaunchKernelGGL((k_zinv_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, g, b.v, b.eta, b.dv,
-                       b.umean, b.wmean, (C<T>*)b.zb);
+    dim3 grid((B.g.nj + JB - 1) / JB, B.g.nr, B.count);
+    hipLaunchKernelGGL((k_zinv_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, B.inst);
 }
 template <typename T, int N>
-void zfwd_lane(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+void zfwd_lane(const Batch& B, hipStream_t s) {
     constexpr int JB = zlane_cols(N);
-    dim3 grid((g.nj + JB - 1) / JB, g.nr);
-    hipLaunchKernelGGL((k_zfwd_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, g, (const C<T>*)b.pb,
-                       (C<T>*)b.ps);
+    dim3 grid((B.g.nj + JB - 1) / JB, B.g.nr, B.count);
+    hipLaunchKernelGGL((k_zfwd_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, B.inst);
 }
 template <typename T, int N>
-void theta_lane(const DevGeom& g, const DevBuf& b, hipStream_t s) {
+void theta_lane(const Batch& B, hipStream_t s) {
     constexpr int W = 64 / lane::Plan<N>::TL;
-    dim3 grid((g.nz / 2 + W - 1) / W, g.nr);
-    hipLaunchKernelGGL((k_theta_lane<T, N>), grid, dim3(192), 0, s, g, (const C<T>*)b.zb, (C<T>*)b.pb);
+    dim3 grid((B.g.nz / 2 + W - 1) / W, B.g.nr, B.count);
+    hipLaunchKernelGGL((k_theta_lane<T, N>), grid, dim3(192), 0, s, B.inst);
 }
 
 template <typename T>
-bool zinv_fast(const DevGeom& g, const DevBuf& b, hipStream_t s) {
-    switch (g.nz) {
-#define TC_CASE(N) case N: zinv_lane<T, N>(g, b, s); return true;
+bool zinv_fast(const Batch& B, hipStream_t s) {
+    switch (B.g.nz) {
+#define TC_CASE(N) case N: zinv_lane<T, N>(B, s); return true;
         TC_LANE_SIZES(TC_CASE)
 #undef TC_CASE
     }
     return false;
 }
 template <typename T>
-bool zfwd_fast(const DevGeom& g, const DevBuf& b, hipStream_t s) {
-    switch (g.nz) {
-#define TC_CASE(N) case N: zfwd_lane<T, N>(g, b, s); return true;
+bool zfwd_fast(const Batch& B, hipStream_t s) {
+    switch (B.g.nz) {
+#define TC_CASE(N) case N: zfwd_lane<T, N>(B, s); return true;
         TC_LANE_SIZES(TC_CASE)
 #undef TC_CASE
     }
     return false;
 }
 template <typename T>
-bool theta_fast(const DevGeom& g, const DevBuf& b, hipStream_t s) {
-    switch (g.ntheta) {
-#define TC_CASE(N) case N: theta_lane<T, N>(g, b, s); return true;
+bool theta_fast(const Batch& B, hipStream_t s) {
+    switch (B.g.ntheta) {
+#define TC_CASE(N) case N: theta_lane<T, N>(B, s); return true;
         TC_LANE_SIZES(TC_CASE)
 #undef TC_CASE
     }
     return false;
 }
 
-void launch_zinv(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
-    if (!g.generic_fft && (fp32 ? zinv_fast<float>(g, b, s) : zinv_fast<double>(g, b, s))) return;
+void launch_zinv(const Batch& B, bool fp32, hipStream_t s) {
+    const DevGeom& g = B.g;
+    if (!g.generic_fft && (fp32 ? zinv_fast<float>(B, s) : zinv_fast<double>(B, s))) return;
     const int jb = zcols_per_block(g.nz, g.nj);
-    dim3 grid((g.nj + jb - 1) / jb, g.nr);
-    if (fp32) {
-        size_t lds = (size_t)jb * g.nz * sizeof(C<float>);
-        hipLaunchKernelGGL(k_zinv<float>, grid, dim3(NT), lds, s, g, b.v, b.eta, b.dv, b.umean, b.wmean,
-                           (C<float>*)b.zb, jb);
-    } else {
-        size_t lds = (size_t)jb * g.nz * sizeof(C<double>);
-        hipLaunchKernelGGL(k_zinv<double>, grid, dim3(NT), lds, s, g, b.v, b.eta, b.dv, b.umean, b.wmean,
-                           (C<double>*)b.zb, jb);
-    }
-}
-
-void launch_theta(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
-    if (!g.generic_fft && (fp32 ? theta_fast<float>(g, b, s) : theta_fast<double>(g, b, s))) return;
-    dim3 grid(g.nz / 2, g.nr);
-    if (fp32) {
-        size_t lds = (size_t)3 * g.ntheta * sizeof(C<float>);
-        hipLaunchKernelGGL(k_theta<float>, grid, dim3(NT), lds, s, g, (const C<float>*)b.zb, (C<float>*)b.pb);
-    } else {
-        size_t lds = (size_t)3 * g.ntheta * sizeof(C<double>);
-        hipLaunchKernelGGL(k_theta<double>, grid, dim3(NT), lds, s, g, (const C<double>*)b.zb, (C<double>*)b.pb);
-    }
-}
-
-void launch_zfwd(const DevGeom& g, const DevBuf& b, bool fp32, hipStream_t s) {
-    if (!g.generic_fft && (fp32 ? zfwd_fast<float>(g, b, s) : zfwd_fast<double>(g, b, s))) return;
-    const int jb = zcols_per_block(g.nz, g.nj);
-    dim3 grid((g.nj + jb - 1) / jb, g.nr);
-    if (fp32) {
-        size_t lds = (size_t)jb * g.nz * sizeof(C<float>);
-        hipLaunchKernelGGL(k_zfwd<float>, grid, dim3(NT), lds, s, g, (const C<float>*)b.pb, (C<float>*)b.ps, jb);
-    } else {
-        size_t lds = (size_t)jb * g.nz * sizeof(C<double>);
-        hipLaunchKernelGGL(k_zfwd<double>, grid, dim3(NT), lds, s, g, (const C<double>*)b.pb, (C<double>*)b.ps, jb);
-    }
-}
-
-void launch_rhs(const DevGeom& g, const DevBuf& b, bool fp32, const StepCoef& c, hipStream_t s) {
-    const size_t total = (size_t)((g.nr + RHS_ROWS - 1) / RHS_ROWS) * g.P;
-    dim3 grid((unsigned)((total + NT - 1) / NT));
+    dim3 grid((g.nj + jb - 1) / jb, g.nr, B.count);
     if (fp32)
-        hipLaunchKernelGGL(k_rhs<float>, grid, dim3(NT), 0, s, g, b, (const C<float>*)b.ps, c);
+        hipLaunchKernelGGL(k_zinv<float>, grid, dim3(NT), (size_t)jb * g.nz * sizeof(C<float>), s, B.inst, jb);
     else
-        hipLaunchKernelGGL(k_rhs<double>, grid, dim3(NT), 0, s, g, b, (const C<double>*)b.ps, c);
+        hipLaunchKernelGGL(k_zinv<double>, grid, dim3(NT), (size_t)jb * g.nz * sizeof(C<double>), s, B.inst, jb);
+}
+
+void launch_theta(const Batch& B, bool fp32, hipStream_t s) {
+    const DevGeom& g = B.g;
+    if (!g.generic_fft && (fp32 ? theta_fast<float>(B, s) : theta_fast<double>(B, s))) return;
+    dim3 grid(g.nz / 2, g.nr, B.count);
+    if (fp32)
+        hipLaunchKernelGGL(k_theta<float>, grid, dim3(NT), (size_t)3 * g.ntheta * sizeof(C<float>), s, B.inst);
+    else
+        hipLaunchKernelGGL(k_theta<double>, grid, dim3(NT), (size_t)3 * g.ntheta * sizeof(C<double>), s, B.inst);
+}
+
+void launch_zfwd(const Batch& B, bool fp32, hipStream_t s) {
+    const DevGeom& g = B.g;
+    if (!g.generic_fft && (fp32 ? zfwd_fast<float>(B, s) : zfwd_fast<double>(B, s))) return;
+    const int jb = zcols_per_block(g.nz, g.nj);
+    dim3 grid((g.nj + jb - 1) / jb, g.nr, B.count);
+    if (fp32)
+        hipLaunchKernelGGL(k_zfwd<float>, grid, dim3(NT), (size_t)jb * g.nz * sizeof(C<float>), s, B.inst, jb);
+    else
+        hipLaunchKernelGGL(k_zfwd<double>, grid, dim3(NT), (size_t)jb * g.nz * sizeof(C<double>), s, B.inst, jb);
+}
+
+template <typename TP>
+void launch_rhs_t(const Batch& B, const StepCoef& c, int k, hipStream_t s) {
+    const DevGeom& g = B.g;
+    const int rr = rhs_rows(g.nr);
+    const size_t total = (size_t)((g.nr - 4 + rr - 1) / rr) * ((g.P + 63) & ~63);
+    dim3 grid((unsigned)((total + NT - 1) / NT), 1, B.count);
+    if (k == 0) hipLaunchKernelGGL((k_rhs<TP, 0>), grid, dim3(NT), 0, s, B.inst, c, rr);
+    else if (k == 1) hipLaunchKernelGGL((k_rhs<TP, 1>), grid, dim3(NT), 0, s, B.inst, c, rr);
+    else hipLaunchKernelGGL((k_rhs<TP, 2>), grid, dim3(NT), 0, s, B.inst, c, rr);
+}
+
+void launch_rhs(const Batch& B, bool fp32, const StepCoef& c, int k, hipStream_t s) {
+    if (fp32)
+        launch_rhs_t<float>(B, c, k, s);
+    else
+        launch_rhs_t<double>(B, c, k, s);
 }
 
 void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, hipStream_t s) {
@@ -1382,9 +1584,10 @@ void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, 
     hipLaunchKernelGGL(k_factor, grid, dim3(SOLVE_NT), 0, s, g, b, c, k);
 }
 
-void launch_solve(const DevGeom& g, const DevBuf& b, int k, hipStream_t s) {
-    dim3 grid((g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2);
-    hipLaunchKernelGGL(k_solve_lu, grid, dim3(SOLVE_NT), 0, s, g, b, k);
+void launch_solve(const Batch& B, int k, hipStream_t s) {
+    // grid.y selects the equation, grid.z the instance
+    dim3 grid((B.g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2, B.count);
+    hipLaunchKernelGGL(k_solve_lu, grid, dim3(SOLVE_NT), 0, s, B.inst, k);
 }
 
 void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>* w, hipStream_t s) {

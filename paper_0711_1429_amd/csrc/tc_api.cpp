@@ -32,6 +32,14 @@ struct Instance {
     double time = 0.0;
     long long steps = 0;
     int red_blocks = 1;
+    const InstDev* self = nullptr;  // this instance's entry in its class array
+};
+
+// Instances that run in the same launches (same grid shape and transform path).
+struct ShapeClass {
+    DevGeom g{};
+    std::vector<int> members;
+    InstDev* dev = nullptr;
 };
 
 struct TimedLaunch {
@@ -43,6 +51,12 @@ struct TimedLaunch {
 
 struct tc_ctx {
     std::vector<Instance> inst;
+    std::vector<ShapeClass> classes;
+    std::vector<void*> allocs;          // class arrays
+    double* hflags = nullptr;           // pinned: one non-finite flag per instance
+    bool use_graphs = true;
+    hipGraphExec_t step_graph = nullptr;  // one full step of every instance
+    hipStream_t graph_stream = nullptr;
     bool dryrun = false;
     bool fp32 = false;
     hipStream_t own = nullptr;
@@ -123,12 +137,11 @@ int check_launch(tc_ctx* c, const char* what) {
     return TC_OK;
 }
 
-StepCoef step_coef(const Instance& in, int k) {
+StepCoef step_coef(int k) {
     StepCoef sc;
-    sc.dt = in.s.g.dt;
     sc.gamma = kGamma[k];
     sc.rho = kRho[k];
-    sc.bdt_nu = 0.5 * (kGamma[k] + kRho[k]) * sc.dt * in.s.nu;
+    sc.beta = 0.5 * (kGamma[k] + kRho[k]);
     return sc;
 }
 
@@ -169,6 +182,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     g.npairs = s.nj * (s.kz + 1);
     g.nu = s.nu;
     g.w_outer = s.w_outer;
+    g.dt = s.g.dt;
     auto plan = [](const FftPlan& p) {
         FftPlanDev d{};
         d.n = p.n;
@@ -206,7 +220,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     const size_t Q = (size_t)s.nr * s.nz * s.nj;
     const size_t cz = c->fp32 ? sizeof(C<float>) : sizeof(C<double>);
     DevBuf& b = in.b;
-    C<double>** c128[] = {&b.v, &b.eta, &b.nv, &b.neta, &b.dv, &b.rv, &b.re};
+    C<double>** c128[] = {&b.v, &b.eta, &b.nv[0], &b.neta[0], &b.nv[1], &b.neta[1], &b.dv, &b.rv, &b.re};
     for (auto p : c128)
         if ((rc = dev_alloc(c, in, p, S))) return rc;
     if ((rc = dev_alloc(c, in, &b.umean, s.nr))) return rc;
@@ -232,7 +246,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     HIPCHK(c, hipMemset(b.lu, 0, (size_t)3 * 2 * 5 * s.nr * g.npairs * sizeof(double)));
     HIPCHK(c, hipMemset(b.fold, 0, (size_t)3 * 2 * 2 * g.npairs * sizeof(double)));
     HIPCHK(c, hipMemset(b.mwall, 0, (size_t)3 * 2 * s.nr * sizeof(double)));
-    for (int k = 0; k < 3; ++k) launch_factor(g, b, step_coef(in, k), k, c->stream);
+    for (int k = 0; k < 3; ++k) launch_factor(g, b, step_coef(k), k, c->stream);
     if (int e = check_launch(c, "factor launch")) return e;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return TC_OK;
@@ -253,29 +267,91 @@ int need_device(tc_ctx* c) {
     return TC_OK;
 }
 
+Batch batch_of(const ShapeClass& cl) { return Batch{cl.dev, (int)cl.members.size(), cl.g}; }
+Batch batch_of(const Instance& in) { return Batch{in.self, 1, in.g}; }
+
 int run_substep(tc_ctx* c, int k) {
-    for (auto& in : c->inst) {
-        const StepCoef sc = step_coef(in, k);
-        const DevGeom& g = in.g;
-        const DevBuf& b = in.b;
-        hipStream_t s = c->stream;
-        timed(c, K_DV, [&] { launch_dv(g, b, s); });
-        timed(c, K_ZINV, [&] { launch_zinv(g, b, c->fp32, s); });
-        timed(c, K_THETA, [&] { launch_theta(g, b, c->fp32, s); });
-        timed(c, K_ZFWD, [&] { launch_zfwd(g, b, c->fp32, s); });
-        timed(c, K_RHS, [&] { launch_rhs(g, b, c->fp32, sc, s); });
-        timed(c, K_SOLVE, [&] { launch_solve(g, b, k, s); });
+    const StepCoef sc = step_coef(k);
+    hipStream_t s = c->stream;
+    for (auto& cl : c->classes) {
+        const Batch B = batch_of(cl);
+        timed(c, K_DV, [&] { launch_dv(B, s); });
+        timed(c, K_ZINV, [&] { launch_zinv(B, c->fp32, s); });
+        timed(c, K_THETA, [&] { launch_theta(B, c->fp32, s); });
+        timed(c, K_ZFWD, [&] { launch_zfwd(B, c->fp32, s); });
+        timed(c, K_RHS, [&] { launch_rhs(B, c->fp32, sc, k, s); });
+        timed(c, K_SOLVE, [&] { launch_solve(B, k, s); });
     }
     return check_launch(c, "substep launch");
 }
 
 int products_only(tc_ctx* c, Instance& in) {
     hipStream_t s = c->stream;
-    launch_dv(in.g, in.b, s);
-    launch_zinv(in.g, in.b, c->fp32, s);
-    launch_theta(in.g, in.b, c->fp32, s);
-    launch_zfwd(in.g, in.b, c->fp32, s);
+    const Batch B = batch_of(in);
+    launch_dv(B, s);
+    launch_zinv(B, c->fp32, s);
+    launch_theta(B, c->fp32, s);
+    launch_zfwd(B, c->fp32, s);
     return check_launch(c, "product launch");
+}
+
+// Group instances by launch shape and upload the per-class instance arrays.
+int build_classes(tc_ctx* c) {
+    for (int i = 0; i < (int)c->inst.size(); ++i) {
+        const DevGeom& g = c->inst[i].g;
+        ShapeClass* found = nullptr;
+        for (auto& cl : c->classes)
+            if (cl.g.nr == g.nr && cl.g.ntheta == g.ntheta && cl.g.nz == g.nz && cl.g.generic_fft == g.generic_fft)
+                found = &cl;
+        if (!found) {
+            c->classes.push_back(ShapeClass{});
+            found = &c->classes.back();
+            found->g = g;
+        }
+        found->members.push_back(i);
+    }
+    for (auto& cl : c->classes) {
+        std::vector<InstDev> host(cl.members.size());
+        for (size_t m = 0; m < cl.members.size(); ++m)
+            host[m] = InstDev{c->inst[cl.members[m]].g, c->inst[cl.members[m]].b};
+        void* q = nullptr;
+        HIPCHK(c, hipMalloc(&q, host.size() * sizeof(InstDev)));
+        c->allocs.push_back(q);
+        HIPCHK(c, hipMemcpy(q, host.data(), host.size() * sizeof(InstDev), hipMemcpyHostToDevice));
+        cl.dev = static_cast<InstDev*>(q);
+        for (size_t m = 0; m < cl.members.size(); ++m) c->inst[cl.members[m]].self = cl.dev + m;
+    }
+    return TC_OK;
+}
+
+void drop_graph(tc_ctx* c) {
+    if (c->step_graph) (void)hipGraphExecDestroy(c->step_graph);
+    c->step_graph = nullptr;
+    c->graph_stream = nullptr;
+}
+
+// Capture one full step (3 substeps of every instance) into a graph on the
+// current stream.  The captured work has no memset or host callback nodes.
+int capture_step(tc_ctx* c) {
+    drop_graph(c);
+    hipGraph_t graph = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = TC_OK;
+    for (int k = 0; k < 3 && rc == TC_OK; ++k) rc = run_substep(c, k);
+    hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->step_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c->step_graph = nullptr;
+        return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    c->graph_stream = c->stream;
+    return TC_OK;
 }
 
 // Host checks of loaded fields (see tc_load_fields in tc.h).
@@ -359,15 +435,20 @@ int tc_create(const tc_geometry* g, int n_instances, tc_ctx** out) {
             return fail(nullptr, TC_EDEVICE, "hipStreamCreate failed");
         }
         c->stream = c->own;
-        for (auto& in : c->inst) {
-            int rc = alloc_instance(c, in);
-            if (rc) {
-                std::string m = c->err;
-                for (auto& x : c->inst) free_instance(x);
-                (void)hipStreamDestroy(c->own);
-                delete c;
-                return fail(nullptr, rc, m);
-            }
+        int rc = TC_OK;
+        for (auto& in : c->inst)
+            if ((rc = alloc_instance(c, in))) break;
+        if (!rc) rc = build_classes(c);
+        if (!rc && hipHostMalloc((void**)&c->hflags, sizeof(double) * n_instances) != hipSuccess)
+            rc = fail(c, TC_ENOMEM, "hipHostMalloc of the flag buffer failed");
+        if (rc) {
+            std::string m = c->err;
+            for (auto& x : c->inst) free_instance(x);
+            for (void* p : c->allocs) (void)hipFree(p);
+            if (c->hflags) (void)hipHostFree(c->hflags);
+            (void)hipStreamDestroy(c->own);
+            delete c;
+            return fail(nullptr, rc, m);
         }
     }
     *out = c;
@@ -378,7 +459,10 @@ int tc_destroy(tc_ctx* c) {
     if (!c) return TC_OK;
     if (!c->dryrun) {
         (void)hipStreamSynchronize(c->stream);
+        drop_graph(c);
         for (auto& in : c->inst) free_instance(in);
+        for (void* p : c->allocs) (void)hipFree(p);
+        if (c->hflags) (void)hipHostFree(c->hflags);
         for (auto& t : c->pending) {
             if (t.start) (void)hipEventDestroy(t.start);
             if (t.stop) (void)hipEventDestroy(t.stop);
@@ -396,6 +480,7 @@ int tc_set_stream(tc_ctx* c, void* stream) {
     collect_timing(c);
     (void)hipStreamSynchronize(c->stream);
     c->stream = stream ? static_cast<hipStream_t>(stream) : c->own;
+    drop_graph(c);
     return TC_OK;
 }
 
@@ -428,8 +513,10 @@ int tc_load_fields(tc_ctx* c, int inst, const double* v, const double* eta, cons
     HIPCHK(c, hipMemcpyAsync(in->b.eta, eta, S * 16, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(in->b.umean, um, in->s.nr * 8, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(in->b.wmean, wm, in->s.nr * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemsetAsync(in->b.nv, 0, S * 16, s));
-    HIPCHK(c, hipMemsetAsync(in->b.neta, 0, S * 16, s));
+    for (int q = 0; q < 2; ++q) {
+        HIPCHK(c, hipMemsetAsync(in->b.nv[q], 0, S * 16, s));
+        HIPCHK(c, hipMemsetAsync(in->b.neta[q], 0, S * 16, s));
+    }
     HIPCHK(c, hipStreamSynchronize(s));
     in->time = 0.0;
     in->steps = 0;
@@ -451,25 +538,36 @@ int tc_get_fields(tc_ctx* c, int inst, double* v, double* eta, double* um, doubl
 }
 
 static int finite_check(tc_ctx* c) {
-    int bad = 0;
-    for (auto& in : c->inst) {
+    // every instance's flag lands in pinned host memory; one wait for all
+    const int n = (int)c->inst.size();
+    for (int i = 0; i < n; ++i) {
+        Instance& in = c->inst[i];
         timed(c, K_FINITE, [&] { launch_finite(in.g, in.b, c->stream); });
         if (int rc = check_launch(c, "finite check")) return rc;
-        double flag = 0.0;
-        HIPCHK(c, hipMemcpyAsync(&flag, in.b.stats + 5, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (flag != 0.0) bad = 1;
+        HIPCHK(c, hipMemcpyAsync(c->hflags + i, in.b.stats + 5, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
-    return bad ? fail(c, TC_ENONFINITE, "non-finite values in the state") : TC_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < n; ++i)
+        if (c->hflags[i] != 0.0)
+            return fail(c, TC_ENONFINITE, "non-finite values in the state of instance " + std::to_string(i));
+    return TC_OK;
 }
 
 int tc_step(tc_ctx* c, int nsteps) {
     if (!c) return TC_EINVAL;
     if (int rc = need_device(c)) return rc;
     if (nsteps < 0) return fail(c, TC_EINVAL, "nsteps must be >= 0");
+    // graphs replay whole steps; per-kernel timing needs the eager launches
+    const bool graph = c->use_graphs && !c->timing && nsteps > 0;
+    if (graph && (!c->step_graph || c->graph_stream != c->stream))
+        if (int rc = capture_step(c)) return rc;
     for (int it = 0; it < nsteps; ++it) {
-        for (int k = 0; k < 3; ++k)
-            if (int rc = run_substep(c, k)) return rc;
+        if (graph) {
+            HIPCHK(c, hipGraphLaunch(c->step_graph, c->stream));
+        } else {
+            for (int k = 0; k < 3; ++k)
+                if (int rc = run_substep(c, k)) return rc;
+        }
         for (auto& in : c->inst) {
             in.time += in.s.g.dt;
             in.steps += 1;
@@ -492,7 +590,7 @@ int tc_velocity(tc_ctx* c, int inst, double* u, double* w) {
     if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
     if (int rc = need_device(c)) return rc;
     const size_t S = (size_t)in->s.nr * in->g.P;
-    launch_dv(in->g, in->b, c->stream);
+    launch_dv(batch_of(*in), c->stream);
     // rv / re are scratch between substeps
     launch_velocity(in->g, in->b, in->b.rv, in->b.re, c->stream);
     if (int rc = check_launch(c, "velocity")) return rc;
@@ -524,7 +622,7 @@ int tc_stats(tc_ctx* c, int inst, tc_stats_t* out) {
     Instance* in = get_inst(c, inst);
     if (!in || !out) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
     if (int rc = need_device(c)) return rc;
-    timed(c, K_DV, [&] { launch_dv(in->g, in->b, c->stream); });
+    timed(c, K_DV, [&] { launch_dv(batch_of(*in), c->stream); });
     timed(c, K_ENERGY, [&] { launch_stats(in->g, in->b, c->stream); });
     if (int rc = check_launch(c, "stats")) return rc;
     double st[5];
@@ -575,6 +673,15 @@ int tc_kernel_times(tc_ctx* c, double* ms, long long* calls, int n) {
         if (ms) ms[i] = c->ms[i];
         if (calls) calls[i] = c->calls[i];
     }
+    return TC_OK;
+}
+
+int tc_use_graphs(tc_ctx* c, int enable) {
+    if (!c) return TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    (void)hipStreamSynchronize(c->stream);
+    c->use_graphs = enable != 0;
+    drop_graph(c);
     return TC_OK;
 }
 

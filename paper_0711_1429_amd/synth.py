@@ -93,3 +93,24 @@ WORKLOADS = {
     "tc-turbulent-fp64": dict(zeta=0.883, re=8000.0, nr=129, ntheta=768, nz=384, dt=2e-4,
                               stretch=1.5, amplitude=0.1, seed=2, steps=1000),
 }
+
+
+def batched_instances(n=64, seed=4):
+    """The batched workload: n independent instances with radius ratio
+    ~ U[0.70, 0.98], Re ~ U[500, 4000], N_r in {33, 49, 65} and
+    (N_theta, N_z) in {64x64, 96x64, 128x128}, each drawn uniformly and
+    independently from default_rng(seed) in that order (all radius ratios,
+    then all Re, then all N_r choices, then all shape choices); instance b
+    uses perturbation seed 4000 + b, amplitude 1e-2, dt = 5e-4."""
+    rng = np.random.default_rng(seed)
+    zeta = rng.uniform(0.70, 0.98, n)
+    re = rng.uniform(500.0, 4000.0, n)
+    nr = rng.choice(np.array([33, 49, 65]), n)
+    shapes = [(64, 64), (96, 64), (128, 128)]
+    sh = rng.integers(0, 3, n)
+    out = []
+    for b in range(n):
+        nt, nz = shapes[int(sh[b])]
+        out.append(dict(zeta=float(zeta[b]), re=float(re[b]), nr=int(nr[b]), ntheta=nt, nz=nz, dt=5e-4,
+                        stretch=0.0, amplitude=1e-2, seed=4000 + b, steps=100))
+    return out

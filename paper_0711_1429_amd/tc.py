@@ -76,6 +76,7 @@ _SIGNATURES = {
     "tc_products": (ctypes.c_int, [_P, ctypes.c_int, _D]),
     "tc_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TcStats)]),
     "tc_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "tc_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_kernel_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
     "tc_kernel_count": (ctypes.c_int, []),
     "tc_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -216,6 +217,9 @@ class Solver:
         s = TcStats()
         self._check(self.lib.tc_stats(self.ctx, inst, ctypes.byref(s)))
         return {name: getattr(s, name) for name, _ in TcStats._fields_}
+
+    def use_graphs(self, enable):
+        self._check(self.lib.tc_use_graphs(self.ctx, int(bool(enable))))
 
     def timing(self, enable):
         self._check(self.lib.tc_timing(self.ctx, int(bool(enable))))

@@ -233,3 +233,52 @@ def test_lane_and_generic_paths_agree_at_turbulent_size():
         err = rel_l2(pa[k], pb_[k])
         print("lane vs generic", k, f"{err:.2e}", flush=True)
         assert err < 1e-13
+
+
+def test_graph_replays_match_eager_steps():
+    """Whole-step graph replays, with eager work (field reads) and
+    synchronisation between them, give bit-identical states to eager launches."""
+    w = workload("tc-medium-fp64")
+    _, a = pair(w)
+    _, b = pair(w)
+    b.use_graphs(False)
+    for s in range(4):
+        a.step(1)
+        b.step(1)
+        fa, fb = a.get_fields(), b.get_fields()
+        for x, y in zip(fa, fb):
+            assert np.array_equal(x, y), s
+    a.step(3)
+    b.step(3)
+    for x, y in zip(a.get_fields(), b.get_fields()):
+        assert np.array_equal(x, y)
+
+
+def test_batched_instances_equal_single_runs():
+    """A context holding several instances of different shapes (several per
+    launch) gives each instance exactly the state it has when run alone; one
+    of them is also checked against the oracle."""
+    from paper_0711_1429_amd.synth import batched_instances
+    from tests.helpers import abi_geometry, fields_for
+    ws = batched_instances(64)[:6] + [dict(workload("tc-small-fp64"), amplitude=1e-2)]
+    for prec in (tcb.TC_PREC_FP64, tcb.TC_PREC_MIXED):
+        multi = tcb.Solver([abi_geometry(w, prec) for w in ws])
+        singles = [tcb.Solver(abi_geometry(w, prec)) for w in ws]
+        for i, w in enumerate(ws):
+            f = fields_for(w, multi.grid(i))
+            multi.load_fields(*f, inst=i)
+            singles[i].load_fields(*f)
+        multi.step(3)
+        for i, one in enumerate(singles):
+            one.step(3)
+            for x, y in zip(multi.get_fields(i), one.get_fields()):
+                assert np.array_equal(x, y), (prec, i)
+    orc, _ = pair(ws[0])
+    orc.step(3)
+    multi = tcb.Solver([abi_geometry(w) for w in ws])
+    for i, w in enumerate(ws):
+        multi.load_fields(*fields_for(w, multi.grid(i)), inst=i)
+    multi.step(3)
+    v, e, um, wm = multi.get_fields(0)
+    rv, re_, rum, rwm = orc.fields()
+    assert rel_l2(v, rv) < TOL and rel_l2(e, re_) < TOL
