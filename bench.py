@@ -35,6 +35,9 @@ def parse():
     p.add_argument("--precision", choices=("fp64", "mixed"), default=None,
                    help="default: fp64, or mixed for the batched workload")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--eager", action="store_true",
+                   help="launch every kernel from the host instead of replaying the step graph "
+                        "(for profilers that see only host-launched kernels)")
     p.add_argument("--cpu-modes", type=int, default=4096,
                    help="modes the CPU baseline solves radially (the transforms cover the whole grid)")
     p.add_argument("--copy-calib", action="store_true",
@@ -162,6 +165,8 @@ def main():
     geos = [tc.make_geometry(zeta=w["zeta"], re=w["re"], nr=w["nr"], ntheta=w["ntheta"], nz=w["nz"],
                              dt=w["dt"], stretch=w["stretch"], precision=prec) for w in ws]
     solver = tc.Solver(geos)
+    if args.eager:
+        solver.use_graphs(False)
     for i, w in enumerate(ws):
         solver.load_fields(*initial_fields(solver.grid(i), w["zeta"], w["ntheta"], w["nz"], w["amplitude"],
                                            w["seed"]), inst=i)

@@ -1200,37 +1200,59 @@ constexpr int zlane_pitch(int N) {
     return N + ((16 % jb) == 0 ? 16 / jb : 1);
 }
 
-// theta rows: three wavefronts per block, wavefront f owning field f
-// (u, v, w) of W = 64 / TL packed row pairs (z0, z0 + 1).  Each wavefront
-// inverse-transforms its field, the physical fields meet in LDS, and each
-// wavefront then forms and forward-transforms two of the six products.
+// Wavefront-scope ordering of LDS accesses: a wavefront's LDS instructions
+// execute in order, so a fence that keeps the compiler from moving them
+// across this point is all that lanes of one wavefront need to exchange data.
+struct WaveSync {
+    __device__ __forceinline__ void operator()() const {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
+
+// register slot that holds position g + TL m after a transform kept in
+// registers (inverse of last_slot_to_m)
+template <int N>
+__host__ __device__ constexpr int m_to_last_slot(int m) {
+    for (int s = 0; s < lane::Plan<N>::P; ++s)
+        if (lane::last_slot_to_m<N>(s) == m) return s;
+    return 0;
+}
+
+constexpr int THETA_NW = 4;  // wavefronts per block of the theta kernel
+
+// theta rows: each wavefront owns W = 64 / TL packed row pairs (z0, z0 + 1)
+// and does everything for them.  It loads u, v and w, inverse-transforms them
+// in turn (the results stay in registers, in the same slot order for all
+// three), forms each of the six products pointwise in registers and
+// forward-transforms it through its own LDS region.  The wavefronts of a
+// block share only the twiddle table, so no block-wide barrier follows it.
 template <typename T, int N>
-__global__ __launch_bounds__(192) void k_theta_lane(const InstDev* __restrict__ I) {
+__global__ __launch_bounds__(64 * THETA_NW) __attribute__((amdgpu_waves_per_eu(2))) void k_theta_wave(
+    const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
     const C<T>* __restrict__ zb = (const C<T>*)b.zb;
     C<T>* __restrict__ pb = (C<T>*)b.pb;
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
-    __shared__ C<T> lds[3 * W * N];
-    const int f = threadIdx.x / 64;             // field of this wavefront
-    const int lw = threadIdx.x - f * 64;        // lane within the wavefront
+    __shared__ C<T> lds[THETA_NW * W * N];
+    __shared__ C<T> twl[lane::tw_size<N>() + 1];  // per-pass twiddles
+    const int wv = threadIdx.x / 64;
+    const int lw = threadIdx.x - wv * 64;
     const int grp = lw / TL;
     const int gl = lw - grp * TL;
-    const int rp = blockIdx.x * W + grp;
-    const int nz = g.nz, kt = g.kt, nj = g.nj;
-    const bool active = rp < nz / 2;  // idle groups still reach every barrier
+    const int rp = (blockIdx.x * THETA_NW + wv) * W + grp;
+    const int nz = g.nz, kt = g.kt, nj = g.nj, nr = g.nr;
+    const bool active = rp < nz / 2;
     const int r = blockIdx.y;
     const int z0 = 2 * rp;
-    const T* tw = tw_t<T>(g);
-    const DevSync sync;
-    C<T>* mine = lds + (f * W + grp) * N;       // this group's region
-    __shared__ C<T> twl[lane::tw_size<N>() + 1];  // per-pass twiddles in LDS
-    lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, 192);
-    sync();
-    {
-        C<T> x[P];
-        const C<T>* row0 = zb + (((size_t)f * g.nr + r) * nz + z0) * nj;
+    lane::fill_twiddles<T, N>(twl, tw_t<T>(g), threadIdx.x, 64 * THETA_NW);
+    // the z-spectral rows of field fl packed into the complex sequence of the
+    // two real rows (z0, z0 + 1)
+    auto load = [&](int fl, C<T>* x) {
+        const C<T>* row0 = zb + (((size_t)fl * nr + r) * nz + z0) * nj;
         const C<T>* row1 = row0 + nj;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -1238,52 +1260,32 @@ __global__ __launch_bounds__(192) void k_theta_lane(const InstDev* __restrict__ 
             C<T> h = {(T)0, (T)0};
             if (active) {
                 if (p <= kt) {
-                    C<T> a = row0[p], b = row1[p];
+                    C<T> a = row0[p], c = row1[p];
                     if (p == 0) {
                         a.y = (T)0;
-                        b.y = (T)0;
+                        c.y = (T)0;
                     }
-                    h = C<T>{a.x - b.y, a.y + b.x};
+                    h = C<T>{a.x - c.y, a.y + c.x};
                 } else if (p >= N - kt) {
-                    const C<T> a = row0[N - p], b = row1[N - p];
-                    h = C<T>{a.x + b.y, b.x - a.y};
+                    const C<T> a = row0[N - p], c = row1[N - p];
+                    h = C<T>{a.x + c.y, c.x - a.y};
                 }
             }
             x[k] = h;
         }
-        lane::fft<T, N, +1, true>(mine, x, gl, twl, sync);
+    };
+    C<T>* mine = lds + (wv * W + grp) * N;
+    const WaveSync sync;
+    // forward-transform product x (slot order of the inverse transforms) and
+    // write its two z rows
+    auto product_out = [&](int prod, const C<T>* a, const C<T>* c) {
+        C<T> x[P];
 #pragma unroll
-        for (int s = 0; s < P; ++s) mine[gl + TL * lane::last_slot_to_m<N>(s)] = x[s];
-    }
-    sync();
-    // products owned by wavefront f: (0,0),(0,1) | (0,2),(1,1) | (1,2),(2,2)
-    const int pa = 2 * f, pbi = 2 * f + 1;
-    const int a0 = f == 0 ? 0 : (f == 1 ? 0 : 1), b0 = f == 0 ? 0 : (f == 1 ? 2 : 2);
-    const int a1 = f == 0 ? 0 : (f == 1 ? 1 : 2), b1 = f == 0 ? 1 : (f == 1 ? 1 : 2);
-    const int idx_a = pa == 0 ? 0 : (pa == 2 ? 2 : 4);   // uu, uw, vw
-    const int idx_b = pbi == 1 ? 1 : (pbi == 3 ? 3 : 5); // uv, vv, ww
-    C<T> x0[P], x1[P];
-    {
-        const C<T>* fa0 = lds + (a0 * W + grp) * N;
-        const C<T>* fb0 = lds + (b0 * W + grp) * N;
-        const C<T>* fa1 = lds + (a1 * W + grp) * N;
-        const C<T>* fb1 = lds + (b1 * W + grp) * N;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const int p = gl + k * TL;
-            x0[k] = pmul(fa0[p], fb0[p]);
-            x1[k] = pmul(fa1[p], fb1[p]);
-        }
-    }
-    sync();
-#pragma unroll
-    for (int which = 0; which < 2; ++which) {
-        C<T>* x = which == 0 ? x0 : x1;
-        const int prod = which == 0 ? idx_a : idx_b;
+        for (int k = 0; k < P; ++k) x[k] = pmul(a[m_to_last_slot<N>(k)], c[m_to_last_slot<N>(k)]);
         lane::fft<T, N, -1, false>(mine, x, gl, twl, sync);
         sync();
         if (active) {
-            C<T>* out = pb + (((size_t)prod * g.nr + r) * nz + z0) * nj;
+            C<T>* out = pb + (((size_t)prod * nr + r) * nz + z0) * nj;
             for (int j = gl; j < nj; j += TL) {
                 const C<T> h = mine[lane::swz<N>(j)];
                 const C<T> hm = mine[lane::swz<N>(j == 0 ? 0 : N - j)];
@@ -1292,7 +1294,23 @@ __global__ __launch_bounds__(192) void k_theta_lane(const InstDev* __restrict__ 
             }
         }
         sync();
-    }
+    };
+    // u and v first, w after the three products that need only u and v, so
+    // that at most three transform-sized register sets are live at a time
+    C<T> u[P], v[P], w[P];
+    load(0, u);
+    load(1, v);
+    __syncthreads();  // twiddle table complete
+    lane::fft<T, N, +1, true>(mine, u, gl, twl, sync);
+    lane::fft<T, N, +1, true>(mine, v, gl, twl, sync);
+    product_out(0, u, u);
+    product_out(1, u, v);
+    load(2, w);
+    product_out(3, v, v);
+    lane::fft<T, N, +1, true>(mine, w, gl, twl, sync);
+    product_out(2, u, w);
+    product_out(4, v, w);
+    product_out(5, w, w);
 }
 
 // inverse z transform of u, v, w for JB j-columns of one plane; v, eta and
@@ -1496,9 +1514,9 @@ void zfwd_lane(const Batch& B, hipStream_t s) {
 }
 template <typename T, int N>
 void theta_lane(const Batch& B, hipStream_t s) {
-    constexpr int W = 64 / lane::Plan<N>::TL;
-    dim3 grid((B.g.nz / 2 + W - 1) / W, B.g.nr, B.count);
-    hipLaunchKernelGGL((k_theta_lane<T, N>), grid, dim3(192), 0, s, B.inst);
+    constexpr int RB = (64 / lane::Plan<N>::TL) * THETA_NW;  // row pairs per block
+    dim3 grid((B.g.nz / 2 + RB - 1) / RB, B.g.nr, B.count);
+    hipLaunchKernelGGL((k_theta_wave<T, N>), grid, dim3(64 * THETA_NW), 0, s, B.inst);
 }
 
 template <typename T>
