@@ -59,6 +59,34 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 5}))
 
 
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter table in
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a device-copy calibration),
+    or None when the table has no row for it or was taken on other kernel
+    sources than the ones built here."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_step_kernels.txt")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft_lane.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_0711_1429_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha, rows = None, {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if not parts or parts[0].startswith("#"):
+                continue
+            if parts[0] == "kernels_sha256":
+                sha = parts[1]
+            elif len(parts) == 5:
+                rows[tuple(parts[:3])] = float(parts[3]) + float(parts[4])
+    if sha != h.hexdigest():
+        return None
+    return rows.get((workload, precision, kernel))
+
+
 def cpu_baseline(w, nmodes_sample):
     """The FP64 oracle on the host: one substep of the same workload, with the
     transforms over the whole grid and the per-mode radial work on a sample of
@@ -220,13 +248,9 @@ def main():
             per_kernel[name] = rec
     dom = max(step_kernels, key=lambda k: ktimes[k][0])
     achieved = per_kernel[dom]["model_GBs"]
-    # whole-substep byte model: each stage reads and writes HBM once
-    model = 0.0
-    for w in ws:
-        nr, nj, nl, nz = w["nr"], (w["ntheta"] - 1) // 3 + 1, 2 * ((w["nz"] - 1) // 3) + 1, w["nz"]
-        S = nr * nj * nl
-        Q = nr * nz * nj
-        model += (448 * S + 288 * Q) if prec == tc.TC_PREC_FP64 else (304 * S + 144 * Q)
+    # whole-substep byte model: each stage reads its inputs and writes its
+    # outputs in HBM once (the sum of the step kernels' algorithmic bytes)
+    model = sum(kbytes[k] for k in step_kernels)
     t_sub = elapsed / substeps
     w0 = ws[0]
     config = ({"workload": args.workload, "instances": len(ws), "shape_classes": ncls, "precision": precision,
@@ -250,7 +274,9 @@ def main():
         "data": "synthetic: laminar Couette profile plus seeded random-phase divergence-free perturbation",
         "config": config,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_bytes": kbytes[dom] / ncls,
+                     "traffic": None if batched else measured_traffic(args.workload, precision, dom)},
         "substep_model": {"bytes": model, "ms_per_substep": t_sub * 1e3,
                           "GBs": model / t_sub / 1e9, "frac": model / t_sub / 1e9 / HBM_PEAK_GBS},
         "ms_per_step_events": elapsed_events / args.steps * 1e3,

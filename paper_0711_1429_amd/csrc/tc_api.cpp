@@ -701,8 +701,10 @@ double tc_kernel_bytes(const tc_ctx* cc, int inst, int id) {
         case K_ZINV: return 48.0 * S + 3.0 * t * Q;           // read v, eta, D v; write 3 fields
         case K_THETA: return 3.0 * t * Q + 6.0 * t * Q;       // read 3 fields; write 6 products
         case K_ZFWD: return 6.0 * t * Q + 6.0 * t * S;        // read 6; write 6 spectra
-        case K_RHS: return 48.0 * S + 6.0 * t * S + 32.0 * S + 32.0 * S + 32.0 * S;
-                    // read v, eta, D v, 6 spectra, N registers; write N registers and RHS
+        case K_RHS:  // read v, eta, D v and 6 spectra, write the RHS of v and eta; the
+                     // N registers are read by substeps 2, 3 and written by 1, 2
+                     // (the average over a step is given)
+            return (48.0 + 6.0 * t + 32.0 * 2.0 / 3.0 + 32.0 * 2.0 / 3.0 + 32.0) * S;
         case K_SOLVE:  // read RHS and the 5 LU fields of both equations, write v, eta
             return 32.0 * S + 80.0 * in->s.nr * in->s.nj * (in->s.kz + 1.0) + 32.0 * S;
         case K_ENERGY: return 48.0 * S;
