@@ -114,7 +114,7 @@ void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>*
 // energy reductions + finite check + statistics into b.stats
 void launch_stats(const DevGeom& g, const DevBuf& b, hipStream_t s);
 // finite check of the state into b.flags[0]
-void launch_finite(const DevGeom& g, const DevBuf& b, hipStream_t s);
+void launch_finite(const Batch& B, hipStream_t s);
 
 // Launch-shape helpers shared by the host code (buffer sizing).
 int zcols_per_block(int nz, int nj);

@@ -1151,7 +1151,9 @@ __global__ __launch_bounds__(RED_NT) void k_stats_final(DevGeom g, DevBuf b, int
     }
 }
 
-__global__ __launch_bounds__(RED_NT) void k_finite(DevGeom g, DevBuf b) {
+__global__ __launch_bounds__(RED_NT) void k_finite(const InstDev* __restrict__ I) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
     __shared__ int sf[RED_NT];
     const size_t total = (size_t)g.nr * g.P;
     int bad = 0;
@@ -1170,12 +1172,18 @@ __global__ __launch_bounds__(RED_NT) void k_finite(DevGeom g, DevBuf b) {
     if (threadIdx.x == 0) b.flags[blockIdx.x] = sf[0];
 }
 
-__global__ void k_flags_final(DevBuf b, int nblocks) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int bad = 0;
-        for (int i = 0; i < nblocks; ++i) bad |= b.flags[i];
-        b.stats[5] = (double)bad;
+__global__ __launch_bounds__(RED_NT) void k_flags_final(const InstDev* __restrict__ I, int nblocks) {
+    const DevBuf b = I[blockIdx.z].b;
+    __shared__ int sf[RED_NT];
+    int bad = 0;
+    for (int i = threadIdx.x; i < nblocks; i += RED_NT) bad |= b.flags[i];
+    sf[threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = RED_NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sf[threadIdx.x] |= sf[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) b.stats[5] = (double)sf[0];
 }
 
 // ===================================================== lane-FFT fast path
@@ -1619,10 +1627,11 @@ void launch_stats(const DevGeom& g, const DevBuf& b, hipStream_t s) {
     hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(RED_NT), 0, s, g, b, nb);
 }
 
-void launch_finite(const DevGeom& g, const DevBuf& b, hipStream_t s) {
-    const int nb = reduction_blocks(g);
-    hipLaunchKernelGGL(k_finite, dim3(nb), dim3(RED_NT), 0, s, g, b);
-    hipLaunchKernelGGL(k_flags_final, dim3(1), dim3(64), 0, s, b, nb);
+// non-finite flag of every instance of a shape class into its stats[5]
+void launch_finite(const Batch& B, hipStream_t s) {
+    const int nb = reduction_blocks(B.g);
+    hipLaunchKernelGGL(k_finite, dim3(nb, 1, B.count), dim3(RED_NT), 0, s, B.inst);
+    hipLaunchKernelGGL(k_flags_final, dim3(1, 1, B.count), dim3(RED_NT), 0, s, B.inst, nb);
 }
 
 }  // namespace tc

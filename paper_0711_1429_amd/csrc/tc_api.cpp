@@ -2,6 +2,7 @@
 // field I/O with validation, the substep sequence and statistics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -49,8 +50,17 @@ struct TimedLaunch {
 
 }  // namespace
 
+// a side stream of the step graph and the event that joins it back
+struct Branch {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+};
+constexpr int kMaxBranches = 16;
+
 struct tc_ctx {
     std::vector<Instance> inst;
+    std::vector<Branch> branch;         // step-graph branches (several shape classes)
+    hipEvent_t fork = nullptr;
     std::vector<ShapeClass> classes;
     std::vector<void*> allocs;          // class arrays
     double* hflags = nullptr;           // pinned: one non-finite flag per instance
@@ -270,18 +280,20 @@ int need_device(tc_ctx* c) {
 Batch batch_of(const ShapeClass& cl) { return Batch{cl.dev, (int)cl.members.size(), cl.g}; }
 Batch batch_of(const Instance& in) { return Batch{in.self, 1, in.g}; }
 
-int run_substep(tc_ctx* c, int k) {
+// Substep k of one shape class on stream s.
+void class_substep(tc_ctx* c, const ShapeClass& cl, int k, hipStream_t s) {
     const StepCoef sc = step_coef(k);
-    hipStream_t s = c->stream;
-    for (auto& cl : c->classes) {
-        const Batch B = batch_of(cl);
-        timed(c, K_DV, [&] { launch_dv(B, s); });
-        timed(c, K_ZINV, [&] { launch_zinv(B, c->fp32, s); });
-        timed(c, K_THETA, [&] { launch_theta(B, c->fp32, s); });
-        timed(c, K_ZFWD, [&] { launch_zfwd(B, c->fp32, s); });
-        timed(c, K_RHS, [&] { launch_rhs(B, c->fp32, sc, k, s); });
-        timed(c, K_SOLVE, [&] { launch_solve(B, k, s); });
-    }
+    const Batch B = batch_of(cl);
+    timed(c, K_DV, [&] { launch_dv(B, s); });
+    timed(c, K_ZINV, [&] { launch_zinv(B, c->fp32, s); });
+    timed(c, K_THETA, [&] { launch_theta(B, c->fp32, s); });
+    timed(c, K_ZFWD, [&] { launch_zfwd(B, c->fp32, s); });
+    timed(c, K_RHS, [&] { launch_rhs(B, c->fp32, sc, k, s); });
+    timed(c, K_SOLVE, [&] { launch_solve(B, k, s); });
+}
+
+int run_substep(tc_ctx* c, int k) {
+    for (auto& cl : c->classes) class_substep(c, cl, k, c->stream);
     return check_launch(c, "substep launch");
 }
 
@@ -331,13 +343,43 @@ void drop_graph(tc_ctx* c) {
 }
 
 // Capture one full step (3 substeps of every instance) into a graph on the
-// current stream.  The captured work has no memset or host callback nodes.
+// current stream.  Shape classes share no memory, so with several classes
+// each one is captured on a side stream forked from and joined back into the
+// current stream: the graph gets one independent branch per class and the
+// classes run concurrently on replay.  The captured work has no memset or
+// host callback nodes.
 int capture_step(tc_ctx* c) {
     drop_graph(c);
+    const int ncl = (int)c->classes.size();
+    const int nbranch = ncl > 1 ? std::min(ncl, kMaxBranches) : 0;
+    while ((int)c->branch.size() < nbranch) {
+        Branch br;
+        if (hipStreamCreateWithFlags(&br.stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(c, TC_EDEVICE, "hipStreamCreate for a graph branch failed");
+        if (hipEventCreateWithFlags(&br.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(br.stream);
+            return fail(c, TC_EDEVICE, "hipEventCreate for a graph branch failed");
+        }
+        c->branch.push_back(br);
+    }
+    if (nbranch && !c->fork) HIPCHK(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
     hipGraph_t graph = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int rc = TC_OK;
-    for (int k = 0; k < 3 && rc == TC_OK; ++k) rc = run_substep(c, k);
+    if (nbranch) {
+        hipError_t e = hipEventRecord(c->fork, c->stream);
+        for (int b = 0; b < nbranch && e == hipSuccess; ++b) e = hipStreamWaitEvent(c->branch[b].stream, c->fork, 0);
+        for (int ci = 0; ci < ncl && e == hipSuccess; ++ci)
+            for (int k = 0; k < 3; ++k) class_substep(c, c->classes[ci], k, c->branch[ci % nbranch].stream);
+        for (int b = 0; b < nbranch && e == hipSuccess; ++b) {
+            e = hipEventRecord(c->branch[b].done, c->branch[b].stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->branch[b].done, 0);
+        }
+        if (e != hipSuccess) rc = hip_fail(c, e, "graph branch fork/join");
+        else rc = check_launch(c, "substep launch");
+    } else {
+        for (int k = 0; k < 3 && rc == TC_OK; ++k) rc = run_substep(c, k);
+    }
     hipError_t e = hipStreamEndCapture(c->stream, &graph);
     if (rc) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -460,6 +502,11 @@ int tc_destroy(tc_ctx* c) {
     if (!c->dryrun) {
         (void)hipStreamSynchronize(c->stream);
         drop_graph(c);
+        for (auto& br : c->branch) {
+            (void)hipEventDestroy(br.done);
+            (void)hipStreamDestroy(br.stream);
+        }
+        if (c->fork) (void)hipEventDestroy(c->fork);
         for (auto& in : c->inst) free_instance(in);
         for (void* p : c->allocs) (void)hipFree(p);
         if (c->hflags) (void)hipHostFree(c->hflags);
@@ -538,14 +585,14 @@ int tc_get_fields(tc_ctx* c, int inst, double* v, double* eta, double* um, doubl
 }
 
 static int finite_check(tc_ctx* c) {
-    // every instance's flag lands in pinned host memory; one wait for all
+    // one launch pair per shape class; every instance's flag lands in pinned
+    // host memory, with one wait for all
     const int n = (int)c->inst.size();
-    for (int i = 0; i < n; ++i) {
-        Instance& in = c->inst[i];
-        timed(c, K_FINITE, [&] { launch_finite(in.g, in.b, c->stream); });
-        if (int rc = check_launch(c, "finite check")) return rc;
-        HIPCHK(c, hipMemcpyAsync(c->hflags + i, in.b.stats + 5, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    }
+    for (auto& cl : c->classes) timed(c, K_FINITE, [&] { launch_finite(batch_of(cl), c->stream); });
+    if (int rc = check_launch(c, "finite check")) return rc;
+    for (int i = 0; i < n; ++i)
+        HIPCHK(c, hipMemcpyAsync(c->hflags + i, c->inst[i].b.stats + 5, sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < n; ++i)
         if (c->hflags[i] != 0.0)
