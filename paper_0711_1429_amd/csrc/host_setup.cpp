@@ -10,6 +10,7 @@
 // monomials x = (r - r_n)/h and rounded once.
 #include "host_setup.h"
 
+#include <algorithm>
 #include <cmath>
 #include <sstream>
 
@@ -267,6 +268,42 @@ int build_setup(const tc_geometry& g, Setup& s, std::string& err) {
             o[2] = (double)(1.0L / dd);
             o[3] = (double)a;
             o[4] = (double)row[4];
+        }
+    }
+
+    // Segmented sweeps: the centred block (rows 2..nr-3) is cut into
+    // DV_SEGMENTS segments of dv_seg rows.  Inside segment [s0, s1) the
+    // forward recurrence y_n = r_n - l1_n y_{n-1} - l2_n y_{n-2} is the
+    // particular solution from zero carry-in plus y_{s0-1} hf1 + y_{s0-2} hf2,
+    // the backward one x_n = (y_n - u1_n x_{n+1} - u2_n x_{n+2}) / u0_n the
+    // particular solution plus x_{s1} hb1 + x_{s1+1} hb2.
+    {
+        const int nc = nr - 4;
+        int L = 4;
+        while (DV_SEGMENTS * L < nc) L *= 2;
+        s.dv_seg = L <= 16 ? L : 0;
+        s.dvh.assign((size_t)4 * nr, 0.0);
+        if (s.dv_seg) {
+            for (int seg = 0; seg < DV_SEGMENTS; ++seg) {
+                const int s0 = 2 + seg * L, s1 = std::min(s0 + L, nr - 2);
+                for (int which = 0; which < 2; ++which) {
+                    ld a1 = which == 0 ? 1.0L : 0.0L, a2 = which == 0 ? 0.0L : 1.0L;  // y_{n-1}, y_{n-2}
+                    for (int n = s0; n < s1; ++n) {
+                        const ld h = -(ld)s.blu[(size_t)n * 5 + 1] * a1 - (ld)s.blu[(size_t)n * 5 + 0] * a2;
+                        s.dvh[(size_t)which * nr + n] = (double)h;
+                        a2 = a1;
+                        a1 = h;
+                    }
+                    ld b1 = which == 0 ? 1.0L : 0.0L, b2 = which == 0 ? 0.0L : 1.0L;  // x_{n+1}, x_{n+2}
+                    for (int n = s1 - 1; n >= s0; --n) {
+                        const double* o = &s.blu[(size_t)n * 5];
+                        const ld x = (-(ld)o[3] * b1 - (ld)o[4] * b2) * (ld)o[2];
+                        s.dvh[(size_t)(2 + which) * nr + n] = (double)x;
+                        b2 = b1;
+                        b1 = x;
+                    }
+                }
+            }
         }
     }
 

@@ -29,6 +29,8 @@ struct DevGeom {
     const int* sigma;       // [nr]
     const double* coef;     // [5][nr][5]
     const double* blu;      // [nr][5]
+    const double* dvh;      // [4][nr] segment responses of the d0 sweeps
+    int dv_seg;             // rows per segment of the segmented D v kernel, 0: sequential kernel
     const double* m;        // [nj]
     const double* alpha;    // [nl]
     const double* tw_theta; // [ntheta] complex

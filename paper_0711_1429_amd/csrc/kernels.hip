@@ -281,6 +281,132 @@ __global__ __launch_bounds__(NT) void k_dv(const InstDev* __restrict__ I) {
     }
 }
 
+// D v with the d0 system swept in DV_SEGMENTS segments of L rows of the
+// centred block (rows 2..nr-3).  Wavefront w of a block owns segment w of the
+// same 64 modes (one lane per mode), so a mode's segments meet in LDS.  Each
+// lane forms its rows' right-hand sides d1 v from a register window of v,
+// runs the forward recurrence from zero carry-in, and adds the carried-in
+// values times the segment responses (host table dvh) once the chain of
+// segment end values has been resolved through LDS; the back substitution
+// goes the same way in the other direction.  v is read once (plus a 4-row
+// halo per segment), D v written once, and all rows of a mode are in flight
+// together.  The mean slot of v is zero, so it needs no branch.
+template <int L>
+__global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __restrict__ I) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    const cd* __restrict__ v = b.v;
+    cd* __restrict__ dv = b.dv;
+    __shared__ cd xc[DV_SEGMENTS][2][64];
+    const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int lane = threadIdx.x & 63;
+    const int nr = g.nr;
+    const size_t P = g.P;
+    const int m0 = blockIdx.x * 64 + lane;
+    const bool act = m0 < g.P;
+    const size_t mode = act ? m0 : g.P - 1;  // idle lanes read a valid column
+    const int s0 = 2 + seg * L;
+    const int len = max(0, min(s0 + L, nr - 2) - s0);
+    const double* __restrict__ d0 = g.coef;
+    const double* __restrict__ d1 = g.coef + (size_t)nr * 5;
+    const double* __restrict__ blu = g.blu;
+    const double* __restrict__ hf1 = g.dvh;
+    const double* __restrict__ hf2 = g.dvh + nr;
+    const double* __restrict__ hb1 = g.dvh + 2 * nr;
+    const double* __restrict__ hb2 = g.dvh + 3 * nr;
+    cd p[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) p[i] = cd{0, 0};
+    cd e1 = {0, 0}, el = {0, 0};  // D v at rows 1 and nr-2 (explicit rows)
+    if (len > 0) {
+        cd w[L + 4];  // v at rows s0-2 .. s0+L+1 (clamped to the grid)
+#pragma unroll
+        for (int t = 0; t < L + 4; ++t) w[t] = v[(size_t)min(s0 - 2 + t, nr - 1) * P + mode];
+        if (seg == 0)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) e1 = cfma(d1[1 * 5 + j], w[j], e1);
+        if (s0 + len > nr - 4)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) el = cfma(d1[(size_t)(nr - 2) * 5 + j], v[(size_t)(nr - 5 + j) * P + mode], el);
+        cd y1 = {0, 0}, y2 = {0, 0};
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const int n = s0 + i;
+            if (i < len) {
+                const double* k1 = d1 + (size_t)n * 5;
+                cd rhs = cfma(k1[0], w[i], cfma(k1[1], w[i + 1], cfma(k1[2], w[i + 2],
+                         cfma(k1[3], w[i + 3], cfma(k1[4], w[i + 4], cd{0, 0})))));
+                // the known D v at rows 1 and nr-2 move to the right-hand side
+                if (n <= 3) rhs = cfma(-d0[(size_t)n * 5 + (3 - n)], e1, rhs);
+                if (n >= nr - 4) rhs = cfma(-d0[(size_t)n * 5 + (nr - n)], el, rhs);
+                const cd y = cfma(-blu[(size_t)n * 5 + 0], y2, cfma(-blu[(size_t)n * 5 + 1], y1, rhs));
+                p[i] = y;
+                y2 = y1;
+                y1 = y;
+            }
+        }
+    }
+    // forward carries: segment t's end values (y_{t1-1}, y_{t1-2}) with zero carry-in
+    xc[seg][0][lane] = p[L - 1];
+    xc[seg][1][lane] = p[L - 2];
+    __syncthreads();
+    cd c1 = {0, 0}, c2 = {0, 0};  // y_{s0-1}, y_{s0-2}: every earlier segment is full
+    for (int t = 0; t < (len > 0 ? seg : 0); ++t) {
+        const int te = 2 + (t + 1) * L - 1;
+        const cd n1 = cfma(hf1[te], c1, cfma(hf2[te], c2, xc[t][0][lane]));
+        const cd n2 = cfma(hf1[te - 1], c1, cfma(hf2[te - 1], c2, xc[t][1][lane]));
+        c1 = n1;
+        c2 = n2;
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+        if (i < len) p[i] = cfma(hf1[s0 + i], c1, cfma(hf2[s0 + i], c2, p[i]));
+    __syncthreads();  // xc is reused
+    {
+        cd q1 = {0, 0}, q2 = {0, 0};
+#pragma unroll
+        for (int i = L - 1; i >= 0; --i) {
+            if (i < len) {
+                const double* o = blu + (size_t)(s0 + i) * 5;
+                const cd t = cfma(-o[4], q2, cfma(-o[3], q1, p[i]));
+                const cd q = {t.x * o[2], t.y * o[2]};
+                p[i] = q;
+                q2 = q1;
+                q1 = q;
+            }
+        }
+    }
+    // backward carries: (x_{t0}, x_{t0+1}) of segment t with zero carry-in
+    xc[seg][0][lane] = p[0];
+    xc[seg][1][lane] = p[1];
+    __syncthreads();
+    cd d1c = {0, 0}, d2c = {0, 0};  // x_{s1}, x_{s1+1}; zero beyond the last non-empty segment
+    if (!act || len == 0) return;
+    for (int t = DV_SEGMENTS - 1; t > seg; --t) {
+        const int t0 = 2 + t * L;
+        if (t0 >= nr - 2) continue;  // empty segment: carries pass through
+        const cd n1 = cfma(hb1[t0], d1c, cfma(hb2[t0], d2c, xc[t][0][lane]));
+        const cd n2 = cfma(hb1[t0 + 1], d1c, cfma(hb2[t0 + 1], d2c, xc[t][1][lane]));
+        d1c = n1;
+        d2c = n2;
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        if (i < len) {
+            const int n = s0 + i;
+            dv[(size_t)n * P + mode] = cfma(hb1[n], d1c, cfma(hb2[n], d2c, p[i]));
+        }
+    }
+    if (seg == 0) {
+        dv[mode] = cd{0, 0};
+        dv[P + mode] = e1;
+    }
+    if (s0 + len == nr - 2) {
+        dv[(size_t)(nr - 2) * P + mode] = el;
+        dv[(size_t)(nr - 1) * P + mode] = cd{0, 0};
+    }
+}
+
 // ---------------------------------------------------------------- k_zinv
 template <typename T>
 __global__ __launch_bounds__(NT) void k_zinv(const InstDev* __restrict__ I, int jb) {
@@ -1056,6 +1182,182 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve_lu(const InstDev* __restrict
     }
 }
 
+// The same substitutions with each column's rows 1..nr-2 cut into
+// SV_SEGMENTS segments of L rows, one wavefront per segment and one lane per
+// mode (the -l columns of j = 0 are written by their +l lanes as conjugates).
+// Each lane runs the forward recurrence y_n = r_n - l1_n y_{n-1} - l2_n y_{n-2}
+// over its rows from zero carry-in, together with the two real responses to
+// unit carried-in values (from the same l1, l2), publishes the end values and
+// responses in LDS, resolves its true carry-in along the chain of earlier
+// segments and corrects its rows; the back substitution runs the same way
+// from the last segment down.  Every right-hand side, factor and output is
+// read or written once, and all rows of a column are in flight together.
+constexpr int SV_SEGMENTS = 8;
+
+template <int L>
+__global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* __restrict__ I, int k) {
+    const DevGeom g = I[blockIdx.z].g;
+    const DevBuf b = I[blockIdx.z].b;
+    __shared__ cd xc[SV_SEGMENTS][2][64];      // end values of each segment
+    __shared__ double hx[SV_SEGMENTS][4][64];  // end responses of each segment
+    const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int lane = threadIdx.x & 63;
+    const int eqn = blockIdx.y;
+    const int nr = g.nr, kz = g.kz, nl = g.nl;
+    const size_t P = g.P;
+    const int m0 = blockIdx.x * 64 + lane;
+    const int mode = min(m0, g.P - 1);
+    const int j = mode / nl;
+    const int l = mode - j * nl - kz;
+    const int lp = l < 0 ? -l : l;
+    const int pair = j * (kz + 1) + lp;
+    const bool mean = (j == 0 && l == 0);
+    // lanes past the last mode, and the -l columns of j = 0, only take part in
+    // the barriers
+    const bool act = m0 < g.P && !(j == 0 && l < 0);
+    const bool mirror = (j == 0 && l > 0);
+    const int s0 = 1 + seg * L;
+    const int len = max(0, min(s0 + L, nr - 1) - s0);
+    const cd* __restrict__ rhs = eqn == 0 ? b.rv : b.re;
+    cd* __restrict__ out = eqn == 0 ? b.v : b.eta;
+    const double* __restrict__ mwall = b.mwall + ((size_t)k * 2 + eqn) * nr;
+    const double* __restrict__ lu = b.lu;
+    const size_t fstride = (size_t)nr * g.npairs;  // between the five factor fields
+    const double* __restrict__ lub = lu + lu_index(g, k, eqn, 0, 0, pair);
+    auto raw = [&](int n) {  // right-hand side of row n before elimination
+        cd r = rhs[(size_t)n * P + mode];
+        if (mean) r.x -= mwall[n];
+        return r;
+    };
+    cd y[L];
+    double h1[L], h2[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        y[i] = cd{0, 0};
+        h1[i] = 0.0;
+        h2[i] = 0.0;
+    }
+    if (len > 0) {
+        cd r[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) r[i] = raw(min(s0 + i, nr - 2));
+        if (s0 == 1) r[0] = cfma(-b.fold[(((size_t)k * 2 + eqn) * 2 + 0) * g.npairs + pair], raw(2), r[0]);
+        cd p1 = {0, 0}, p2 = {0, 0};
+        double a1 = 1.0, a2 = 0.0, c1 = 0.0, c2 = 1.0;  // responses to y_{s0-1} and y_{s0-2}
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            if (i < len) {
+                const int n = s0 + i;
+                cd rn = r[i];
+                if (n == nr - 2) rn = cfma(-b.fold[(((size_t)k * 2 + eqn) * 2 + 1) * g.npairs + pair], raw(nr - 3), rn);
+                const double l2 = lub[(size_t)n * g.npairs], l1 = lub[fstride + (size_t)n * g.npairs];
+                const cd yn = cfma(-l2, p2, cfma(-l1, p1, rn));
+                const double an = -l1 * a1 - l2 * a2, cn = -l1 * c1 - l2 * c2;
+                y[i] = yn;
+                h1[i] = an;
+                h2[i] = cn;
+                p2 = p1;
+                p1 = yn;
+                a2 = a1;
+                a1 = an;
+                c2 = c1;
+                c1 = cn;
+            }
+        }
+    }
+    xc[seg][0][lane] = y[L - 1];
+    xc[seg][1][lane] = y[L - 2];
+    hx[seg][0][lane] = h1[L - 1];
+    hx[seg][1][lane] = h2[L - 1];
+    hx[seg][2][lane] = h1[L - 2];
+    hx[seg][3][lane] = h2[L - 2];
+    __syncthreads();
+    {
+        cd c1 = {0, 0}, c2 = {0, 0};  // y_{s0-1}, y_{s0-2}; every earlier segment is full
+        for (int t = 0; t < (len > 0 ? seg : 0); ++t) {
+            const cd n1 = cfma(hx[t][0][lane], c1, cfma(hx[t][1][lane], c2, xc[t][0][lane]));
+            const cd n2 = cfma(hx[t][2][lane], c1, cfma(hx[t][3][lane], c2, xc[t][1][lane]));
+            c1 = n1;
+            c2 = n2;
+        }
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+            if (i < len) y[i] = cfma(h1[i], c1, cfma(h2[i], c2, y[i]));
+    }
+    __syncthreads();  // xc, hx are reused
+    // back substitution from zero carry-in, with the responses to x_{s1}, x_{s1+1}
+    {
+        cd q1 = {0, 0}, q2 = {0, 0};
+        double a1 = 1.0, a2 = 0.0, c1 = 0.0, c2 = 1.0;
+#pragma unroll
+        for (int i = L - 1; i >= 0; --i) {
+            if (i < len) {
+                const size_t o = (size_t)(s0 + i) * g.npairs;
+                const double id = lub[2 * fstride + o], u1 = lub[3 * fstride + o], u2 = lub[4 * fstride + o];
+                const cd t = cfma(-u2, q2, cfma(-u1, q1, y[i]));
+                const cd q = {t.x * id, t.y * id};
+                const double an = (-u1 * a1 - u2 * a2) * id, cn = (-u1 * c1 - u2 * c2) * id;
+                y[i] = q;
+                h1[i] = an;
+                h2[i] = cn;
+                q2 = q1;
+                q1 = q;
+                a2 = a1;
+                a1 = an;
+                c2 = c1;
+                c1 = cn;
+            }
+        }
+    }
+    // (x_{s0}, x_{s0+1}) from zero carry-in; for a one-row segment x_{s0+1} is
+    // the carried-in x_{s1} itself, which is zero for the last segment
+    xc[seg][0][lane] = y[0];
+    xc[seg][1][lane] = y[1];
+    hx[seg][0][lane] = h1[0];
+    hx[seg][1][lane] = h2[0];
+    hx[seg][2][lane] = h1[1];
+    hx[seg][3][lane] = h2[1];
+    __syncthreads();
+    if (!act || len == 0) return;
+    cd d1 = {0, 0}, d2 = {0, 0};  // x_{s1}, x_{s1+1}: zero beyond the last non-empty segment
+    for (int t = SV_SEGMENTS - 1; t > seg; --t) {
+        if (1 + t * L >= nr - 1) continue;  // empty segment
+        const cd n1 = cfma(hx[t][0][lane], d1, cfma(hx[t][1][lane], d2, xc[t][0][lane]));
+        const cd n2 = cfma(hx[t][2][lane], d1, cfma(hx[t][3][lane], d2, xc[t][1][lane]));
+        d1 = n1;
+        d2 = n2;
+    }
+    double* mo = eqn == 0 ? b.umean : b.wmean;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        if (i < len) {
+            const int n = s0 + i;
+            const cd x = cfma(h1[i], d1, cfma(h2[i], d2, y[i]));
+            if (mean) {
+                mo[n] = x.x;
+            } else {
+                out[(size_t)n * P + mode] = x;
+                if (mirror) out[(size_t)n * P + (mode - 2 * l)] = cd{x.x, -x.y};
+            }
+        }
+    }
+    // wall rows
+    const bool first = s0 == 1, last = s0 + len == nr - 1;
+    if (mean) {
+        if (first) mo[0] = eqn == 0 ? 0.0 : 1.0;
+        if (last) mo[nr - 1] = eqn == 0 ? 0.0 : g.w_outer;
+    } else {
+        if (first) {
+            out[mode] = cd{0, 0};
+            if (mirror) out[mode - 2 * l] = cd{0, 0};
+        }
+        if (last) {
+            out[(size_t)(nr - 1) * P + mode] = cd{0, 0};
+            if (mirror) out[(size_t)(nr - 1) * P + (mode - 2 * l)] = cd{0, 0};
+        }
+    }
+}
+
 // ---------------------------------------------------------------- reductions
 // Volume-weighted energy density c_j (|u|^2 + |v|^2 + |w|^2) w_n r_n over
 // all (r, mode), block partial sums in a fixed order; also counts non-finite
@@ -1502,6 +1804,12 @@ int reduction_blocks(const DevGeom& g) {
 
 void launch_dv(const Batch& B, hipStream_t s) {
     const DevGeom& g = B.g;
+    const dim3 gseg((g.P + 63) / 64, 1, B.count), bseg(64 * DV_SEGMENTS);
+    switch (g.dv_seg) {
+        case 4: hipLaunchKernelGGL(k_dv_seg<4>, gseg, bseg, 0, s, B.inst); return;
+        case 8: hipLaunchKernelGGL(k_dv_seg<8>, gseg, bseg, 0, s, B.inst); return;
+        case 16: hipLaunchKernelGGL(k_dv_seg<16>, gseg, bseg, 0, s, B.inst); return;
+    }
     dim3 grid((g.P + NT - 1) / NT, 1, B.count);
     hipLaunchKernelGGL(k_dv, grid, dim3(NT), 0, s, B.inst);
 }
@@ -1610,8 +1918,21 @@ void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, 
     hipLaunchKernelGGL(k_factor, grid, dim3(SOLVE_NT), 0, s, g, b, c, k);
 }
 
+// rows per segment of the segmented solve: SV_SEGMENTS * L >= nr - 2, L <= 16
+int solve_segment_rows(int nr) {
+    int L = 4;
+    while (SV_SEGMENTS * L < nr - 2) L *= 2;
+    return L <= 16 ? L : 0;
+}
+
 void launch_solve(const Batch& B, int k, hipStream_t s) {
     // grid.y selects the equation, grid.z the instance
+    const dim3 gseg((B.g.P + 63) / 64, 2, B.count), bseg(64 * SV_SEGMENTS);
+    switch (solve_segment_rows(B.g.nr)) {
+        case 4: hipLaunchKernelGGL(k_solve_seg<4>, gseg, bseg, 0, s, B.inst, k); return;
+        case 8: hipLaunchKernelGGL(k_solve_seg<8>, gseg, bseg, 0, s, B.inst, k); return;
+        case 16: hipLaunchKernelGGL(k_solve_seg<16>, gseg, bseg, 0, s, B.inst, k); return;
+    }
     dim3 grid((B.g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2, B.count);
     hipLaunchKernelGGL(k_solve_lu, grid, dim3(SOLVE_NT), 0, s, B.inst, k);
 }
