@@ -1649,7 +1649,10 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     const double R = g.r[r];
     const size_t Pm = g.P;
     const T* tw = tw_z<T>(g);
-    const DevSync sync;
+    // a column's transform lives in TL lanes of one wavefront, so its LDS
+    // exchanges need only wavefront-scope ordering; the block barriers below
+    // guard the twiddle table and the transposed write-out, which cross columns
+    const WaveSync sync;
     __shared__ C<T> twl[lane::tw_size<N>() + 1];
     lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
     C<T> X[3][P];
@@ -1679,20 +1682,20 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
         X[1][k] = xv;
         X[2][k] = xw;
     }
+    __syncthreads();  // twiddles in place
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        if (f == 0) sync();  // twiddles in place
         lane::fft<T, N, +1, true>(lds + c * PITCH, X[f], gl, twl, sync);
 #pragma unroll
         for (int q = 0; q < P; ++q) lds[c * PITCH + gl + TL * lane::last_slot_to_m<N>(q)] = X[f][q];
-        sync();
+        __syncthreads();
         C<T>* out = zb + ((size_t)f * g.nr + r) * N * nj;
         for (int idx = threadIdx.x; idx < ncols * N; idx += NTH) {
             const int z = idx / ncols;
             const int cc = idx - z * ncols;
             out[(size_t)z * nj + j0 + cc] = lds[cc * PITCH + z];
         }
-        sync();
+        __syncthreads();
     }
 }
 
@@ -1717,7 +1720,9 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
     const size_t Pm = g.P;
     const T scale = (T)(1.0 / ((double)g.ntheta * (double)N));
     const T* tw = tw_z<T>(g);
-    const DevSync sync;
+    // as in k_zinv_lane: wavefront-scope ordering inside a column's transform,
+    // block barriers around the transposed load, which crosses columns
+    const WaveSync sync;
     __shared__ C<T> twl[lane::tw_size<N>() + 1];
     lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
     // the next product's tile (P values per lane) is fetched into registers
@@ -1743,7 +1748,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
             const int cc = idx - z * ncols;
             if (idx < ncols * N) lds[cc * PITCH + z] = nxt[e];
         }
-        sync();
+        __syncthreads();  // also completes the twiddle table on the first pass
         if (f < 5) fetch(f + 1);
         C<T> x[P];
 #pragma unroll
@@ -1759,7 +1764,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
                 if (l >= -kz) out[l + kz] = cscale(x[s], scale);
             }
         }
-        sync();
+        __syncthreads();  // every column read before the next transposed load
     }
 }
 
