@@ -889,12 +889,18 @@ __device__ __forceinline__ void rhs_lane(const cd* __restrict__ v, const cd* __r
     }
 }
 
-// rows per chunk: rr + 4 must be a multiple of 5 and rr <= nr - 4; the
-// longest such chunk up to RHS_MAX_ROWS
+// rows per chunk: rr + 4 must be a multiple of 5 and rr <= nr - 4.  The
+// longest such chunk up to RHS_MAX_ROWS re-reads the least halo; small
+// launches (a few hundred wavefronts) take shorter chunks, trading halo
+// re-reads for wavefronts in flight.
 constexpr int RHS_MAX_ROWS = 21;
-inline int rhs_rows(int nr) {
+constexpr int RHS_MIN_WAVES = 4096;
+inline int rhs_rows(int nr, int P, int count) {
     const int cap = min(nr - 4, RHS_MAX_ROWS);
-    return cap - ((cap - 1) % 5);
+    int rr = cap - ((cap - 1) % 5);
+    const long waves_per_chunk_row = (long)((P + 63) / 64) * count;
+    while (rr > 6 && (long)((nr - 4 + rr - 1) / rr) * waves_per_chunk_row < RHS_MIN_WAVES) rr -= 5;
+    return rr;
 }
 
 template <typename TP, int K>
@@ -1903,7 +1909,7 @@ void launch_zfwd(const Batch& B, bool fp32, hipStream_t s) {
 template <typename TP>
 void launch_rhs_t(const Batch& B, const StepCoef& c, int k, hipStream_t s) {
     const DevGeom& g = B.g;
-    const int rr = rhs_rows(g.nr);
+    const int rr = rhs_rows(g.nr, g.P, B.count);
     const size_t total = (size_t)((g.nr - 4 + rr - 1) / rr) * ((g.P + 63) & ~63);
     dim3 grid((unsigned)((total + NT - 1) / NT), 1, B.count);
     if (k == 0) hipLaunchKernelGGL((k_rhs<TP, 0>), grid, dim3(NT), 0, s, B.inst, c, rr);
