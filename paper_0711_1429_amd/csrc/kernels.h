@@ -31,6 +31,7 @@ struct DevGeom {
     const double* blu;      // [nr][5]
     const double* dvh;      // [4][nr] segment responses of the d0 sweeps
     int dv_seg;             // rows per segment of the segmented D v kernel, 0: sequential kernel
+    int rhs_rr;             // rows per chunk of the RHS kernel
     const double* m;        // [nj]
     const double* alpha;    // [nl]
     const double* tw_theta; // [ntheta] complex
@@ -108,6 +109,16 @@ void launch_zinv(const Batch& B, bool fp32, hipStream_t s);
 void launch_theta(const Batch& B, bool fp32, hipStream_t s);
 void launch_zfwd(const Batch& B, bool fp32, hipStream_t s);
 void launch_rhs(const Batch& B, bool fp32, const StepCoef& c, int k, hipStream_t s);
+
+// Step stages and their launch-group keys: instances whose keys agree share
+// one launch of the stage's kernel (same compile-time variant); the grid then
+// covers the largest member and every block checks its own instance's
+// extents.  A Batch passed to a launcher carries those largest extents.
+enum Stage { ST_DV, ST_ZINV, ST_THETA, ST_ZFWD, ST_RHS, ST_SOLVE, ST_COUNT };
+long long stage_key(int stage, const DevGeom& g);
+// rows per chunk of the RHS kernel for an instance launched with `waves`
+// wavefronts per chunk row in total
+int rhs_rows(int nr, int P, long long waves_per_chunk_row);
 // precomputed LU factors of substep k (run once per context and k)
 void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, hipStream_t s);
 void launch_solve(const Batch& B, int k, hipStream_t s);

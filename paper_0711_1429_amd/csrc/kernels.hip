@@ -298,6 +298,7 @@ __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __re
     const cd* __restrict__ v = b.v;
     cd* __restrict__ dv = b.dv;
     __shared__ cd xc[DV_SEGMENTS][2][64];
+    if ((int)blockIdx.x * 64 >= g.P) return;  // past this instance's modes (whole block)
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x & 63;
     const int nr = g.nr;
@@ -615,7 +616,9 @@ __device__ __forceinline__ cd ldp(const C<TP>* p, size_t i) {
 // the off-centre eta row 1 and the zero row 0, the last chunk the eta row
 // nr-2 and the zero row nr-1.  Lanes are laid out chunk-major over the mode
 // count rounded up to whole wavefronts, so the chunk is wave-uniform and
-// coefficient and grid reads are scalar.
+// coefficient and grid reads are scalar.  The mean (0,0) mode's rows are
+// independent of each other and are done by the blocks with blockIdx.y = 1,
+// one lane per row.
 //
 // The explicit-term registers N alternate between two buffers: substep 0
 // writes n[0] (its rho is zero, so nothing is read), substep 1 reads n[0]
@@ -895,19 +898,18 @@ __device__ __forceinline__ void rhs_lane(const cd* __restrict__ v, const cd* __r
 // re-reads for wavefronts in flight.
 constexpr int RHS_MAX_ROWS = 21;
 constexpr int RHS_MIN_WAVES = 4096;
-inline int rhs_rows(int nr, int P, int count) {
-    const int cap = min(nr - 4, RHS_MAX_ROWS);
-    int rr = cap - ((cap - 1) % 5);
-    const long waves_per_chunk_row = (long)((P + 63) / 64) * count;
-    while (rr > 6 && (long)((nr - 4 + rr - 1) / rr) * waves_per_chunk_row < RHS_MIN_WAVES) rr -= 5;
-    return rr;
-}
 
 template <typename TP, int K>
-__global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepCoef sc, int rr) {
+__global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepCoef sc) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
+    const int rr = g.rhs_rr;
     const C<TP>* __restrict__ ps = (const C<TP>*)b.ps;
+    if (blockIdx.y == 1) {  // the mean (0,0) mode: one lane per row
+        const int n = blockIdx.x * NT + threadIdx.x;
+        if (n < g.nr) rhs_mean_row<TP, K>(g, b, ps, sc, n);
+        return;
+    }
     const int P = g.P;
     const int Pp = (P + 63) & ~63;
     const int nr = g.nr;
@@ -918,18 +920,7 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepC
     if (chunk >= nchunk || mode >= P) return;
     const int n0 = min(2 + chunk * rr, nr - 2 - rr);
     const bool first = chunk == 0, last = chunk == nchunk - 1;
-    if (mode == g.mean) {
-        if (first) {
-            rhs_mean_row<TP, K>(g, b, ps, sc, 0);
-            rhs_mean_row<TP, K>(g, b, ps, sc, 1);
-        }
-        for (int n = n0; n < n0 + rr; ++n) rhs_mean_row<TP, K>(g, b, ps, sc, n);
-        if (last) {
-            rhs_mean_row<TP, K>(g, b, ps, sc, nr - 2);
-            rhs_mean_row<TP, K>(g, b, ps, sc, nr - 1);
-        }
-        return;
-    }
+    if (mode == g.mean) return;  // done by the blockIdx.y == 1 blocks
     const int j = mode / g.nl;
     const int li = mode - j * g.nl;
     rhs_lane<TP, K>(b.v, b.eta, b.dv, ps, K > 0 ? b.nv[K > 0 ? K - 1 : 0] : nullptr,
@@ -1206,6 +1197,7 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
     const DevBuf b = I[blockIdx.z].b;
     __shared__ cd xc[SV_SEGMENTS][2][64];      // end values of each segment
     __shared__ double hx[SV_SEGMENTS][4][64];  // end responses of each segment
+    if ((int)blockIdx.x * 64 >= g.P) return;  // past this instance's modes (whole block)
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x & 63;
     const int eqn = blockIdx.y;
@@ -1555,6 +1547,7 @@ __global__ __launch_bounds__(64 * THETA_NW) __attribute__((amdgpu_waves_per_eu(2
     constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
     __shared__ C<T> lds[THETA_NW * W * N];
     __shared__ C<T> twl[lane::tw_size<N>() + 1];  // per-pass twiddles
+    if ((int)blockIdx.y >= g.nr || (int)blockIdx.x * THETA_NW * W >= g.nz / 2) return;  // whole block
     const int wv = threadIdx.x / 64;
     const int lw = threadIdx.x - wv * 64;
     const int grp = lw / TL;
@@ -1648,6 +1641,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     const int gl = threadIdx.x - c * TL;
     const int r = blockIdx.y;
     const int j0 = blockIdx.x * JB;
+    if (r >= g.nr || j0 >= g.nj) return;  // past this instance's extents (whole block)
     const int nj = g.nj, nl = g.nl, kz = g.kz;
     const int ncols = min(JB, nj - j0);
     const int j = j0 + c;
@@ -1720,6 +1714,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
     const int gl = threadIdx.x - c * TL;
     const int r = blockIdx.y;
     const int j0 = blockIdx.x * JB;
+    if (r >= g.nr || j0 >= g.nj) return;  // past this instance's extents (whole block)
     const int nj = g.nj, nl = g.nl, kz = g.kz;
     const int ncols = min(JB, nj - j0);
     const bool active = c < ncols;
@@ -1874,6 +1869,31 @@ bool theta_fast(const Batch& B, hipStream_t s) {
     return false;
 }
 
+int solve_segment_rows(int nr);
+
+bool lane_length(int n) {
+    switch (n) {
+#define TC_CASE(N) case N: return true;
+        TC_LANE_SIZES(TC_CASE)
+#undef TC_CASE
+    }
+    return false;
+}
+
+long long stage_key(int stage, const DevGeom& g) {
+    // run-time-length transforms launch per exact shape
+    const long long shape = (1LL << 40) | ((long long)g.nr << 24) | ((long long)g.ntheta << 12) | g.nz;
+    switch (stage) {
+        case ST_DV: return g.dv_seg;
+        case ST_ZINV:
+        case ST_ZFWD: return (!g.generic_fft && lane_length(g.nz)) ? g.nz : shape;
+        case ST_THETA: return (!g.generic_fft && lane_length(g.ntheta)) ? g.ntheta : shape;
+        case ST_RHS: return 0;
+        case ST_SOLVE: return solve_segment_rows(g.nr);
+    }
+    return shape;
+}
+
 void launch_zinv(const Batch& B, bool fp32, hipStream_t s) {
     const DevGeom& g = B.g;
     if (!g.generic_fft && (fp32 ? zinv_fast<float>(B, s) : zinv_fast<double>(B, s))) return;
@@ -1906,15 +1926,27 @@ void launch_zfwd(const Batch& B, bool fp32, hipStream_t s) {
         hipLaunchKernelGGL(k_zfwd<double>, grid, dim3(NT), (size_t)jb * g.nz * sizeof(C<double>), s, B.inst, jb);
 }
 
+int rhs_rows(int nr, int P, long long waves_per_chunk_row) {
+    const int cap = min(nr - 4, RHS_MAX_ROWS);
+    int rr = cap - ((cap - 1) % 5);
+    (void)P;
+    while (rr > 6 && (long long)((nr - 4 + rr - 1) / rr) * waves_per_chunk_row < RHS_MIN_WAVES) rr -= 5;
+    return rr;
+}
+
+// B.g carries the largest nr and P and the smallest chunk of the batch, so the
+// grid covers every member; lanes past a member's chunks or modes return.
 template <typename TP>
 void launch_rhs_t(const Batch& B, const StepCoef& c, int k, hipStream_t s) {
     const DevGeom& g = B.g;
-    const int rr = rhs_rows(g.nr, g.P, B.count);
+    const int rr = g.rhs_rr;
     const size_t total = (size_t)((g.nr - 4 + rr - 1) / rr) * ((g.P + 63) & ~63);
-    dim3 grid((unsigned)((total + NT - 1) / NT), 1, B.count);
-    if (k == 0) hipLaunchKernelGGL((k_rhs<TP, 0>), grid, dim3(NT), 0, s, B.inst, c, rr);
-    else if (k == 1) hipLaunchKernelGGL((k_rhs<TP, 1>), grid, dim3(NT), 0, s, B.inst, c, rr);
-    else hipLaunchKernelGGL((k_rhs<TP, 2>), grid, dim3(NT), 0, s, B.inst, c, rr);
+    // grid.y = 1: the mean rows (ceil(nr / NT) of those blocks do work)
+    const unsigned gx = (unsigned)std::max((total + NT - 1) / NT, (size_t)(g.nr + NT - 1) / NT);
+    dim3 grid(gx, 2, B.count);
+    if (k == 0) hipLaunchKernelGGL((k_rhs<TP, 0>), grid, dim3(NT), 0, s, B.inst, c);
+    else if (k == 1) hipLaunchKernelGGL((k_rhs<TP, 1>), grid, dim3(NT), 0, s, B.inst, c);
+    else hipLaunchKernelGGL((k_rhs<TP, 2>), grid, dim3(NT), 0, s, B.inst, c);
 }
 
 void launch_rhs(const Batch& B, bool fp32, const StepCoef& c, int k, hipStream_t s) {

@@ -33,11 +33,20 @@ struct Instance {
     double time = 0.0;
     long long steps = 0;
     int red_blocks = 1;
-    const InstDev* self = nullptr;  // this instance's entry in its class array
+    const InstDev* self = nullptr;  // this instance's entry in the array of all instances
 };
 
-// Instances that run in the same launches (same grid shape and transform path).
+// Instances of the same shape (the non-finite check runs per shape).
 struct ShapeClass {
+    DevGeom g{};
+    std::vector<int> members;
+    InstDev* dev = nullptr;
+};
+
+// Instances that share one launch of a step stage's kernel (equal stage key);
+// g holds the largest extents of the members (see stage_key).
+struct LaunchGroup {
+    long long key = 0;
     DevGeom g{};
     std::vector<int> members;
     InstDev* dev = nullptr;
@@ -62,6 +71,7 @@ struct tc_ctx {
     std::vector<Branch> branch;         // step-graph branches (several shape classes)
     hipEvent_t fork = nullptr;
     std::vector<ShapeClass> classes;
+    std::vector<LaunchGroup> groups[ST_COUNT];
     std::vector<void*> allocs;          // class arrays
     double* hflags = nullptr;           // pinned: one non-finite flag per instance
     bool use_graphs = true;
@@ -280,22 +290,25 @@ int need_device(tc_ctx* c) {
 }
 
 Batch batch_of(const ShapeClass& cl) { return Batch{cl.dev, (int)cl.members.size(), cl.g}; }
+Batch batch_of(const LaunchGroup& gr) { return Batch{gr.dev, (int)gr.members.size(), gr.g}; }
 Batch batch_of(const Instance& in) { return Batch{in.self, 1, in.g}; }
 
-// Substep k of one shape class on stream s.
-void class_substep(tc_ctx* c, const ShapeClass& cl, int k, hipStream_t s) {
-    const StepCoef sc = step_coef(k);
-    const Batch B = batch_of(cl);
-    timed(c, K_DV, [&] { launch_dv(B, s); });
-    timed(c, K_ZINV, [&] { launch_zinv(B, c->fp32, s); });
-    timed(c, K_THETA, [&] { launch_theta(B, c->fp32, s); });
-    timed(c, K_ZFWD, [&] { launch_zfwd(B, c->fp32, s); });
-    timed(c, K_RHS, [&] { launch_rhs(B, c->fp32, sc, k, s); });
-    timed(c, K_SOLVE, [&] { launch_solve(B, k, s); });
+// Stage st of substep k for one launch group on stream s.
+void group_stage(tc_ctx* c, int st, const LaunchGroup& gr, int k, hipStream_t s) {
+    const Batch B = batch_of(gr);
+    switch (st) {
+        case ST_DV: timed(c, K_DV, [&] { launch_dv(B, s); }); break;
+        case ST_ZINV: timed(c, K_ZINV, [&] { launch_zinv(B, c->fp32, s); }); break;
+        case ST_THETA: timed(c, K_THETA, [&] { launch_theta(B, c->fp32, s); }); break;
+        case ST_ZFWD: timed(c, K_ZFWD, [&] { launch_zfwd(B, c->fp32, s); }); break;
+        case ST_RHS: timed(c, K_RHS, [&] { launch_rhs(B, c->fp32, step_coef(k), k, s); }); break;
+        case ST_SOLVE: timed(c, K_SOLVE, [&] { launch_solve(B, k, s); }); break;
+    }
 }
 
 int run_substep(tc_ctx* c, int k) {
-    for (auto& cl : c->classes) class_substep(c, cl, k, c->stream);
+    for (int st = 0; st < ST_COUNT; ++st)
+        for (auto& gr : c->groups[st]) group_stage(c, st, gr, k, c->stream);
     return check_launch(c, "substep launch");
 }
 
@@ -324,7 +337,56 @@ int build_classes(tc_ctx* c) {
         }
         found->members.push_back(i);
     }
+    // RHS chunk length per instance, from the wavefronts of one launch over all instances
+    long long rhs_waves = 0;
+    for (auto& in : c->inst) rhs_waves += (in.g.P + 63) / 64;
+    for (auto& in : c->inst) in.g.rhs_rr = rhs_rows(in.g.nr, in.g.P, rhs_waves);
+    // launch groups per stage, keyed by stage_key; extents are the members' largest
+    for (int st = 0; st < ST_COUNT; ++st) {
+        auto& G = c->groups[st];
+        for (int i = 0; i < (int)c->inst.size(); ++i) {
+            const DevGeom& g = c->inst[i].g;
+            const long long key = stage_key(st, g);
+            LaunchGroup* found = nullptr;
+            for (auto& gr : G)
+                if (gr.key == key) found = &gr;
+            if (!found) {
+                G.push_back(LaunchGroup{});
+                found = &G.back();
+                found->key = key;
+                found->g = g;
+            }
+            DevGeom& m = found->g;
+            m.nr = std::max(m.nr, g.nr);
+            m.nj = std::max(m.nj, g.nj);
+            m.P = std::max(m.P, g.P);
+            m.npairs = std::max(m.npairs, g.npairs);
+            m.rhs_rr = std::min(m.rhs_rr, g.rhs_rr);
+            if (st == ST_THETA) m.nz = std::max(m.nz, g.nz);
+            found->members.push_back(i);
+        }
+        for (auto& gr : G) {
+            std::vector<InstDev> host(gr.members.size());
+            for (size_t q = 0; q < gr.members.size(); ++q)
+                host[q] = InstDev{c->inst[gr.members[q]].g, c->inst[gr.members[q]].b};
+            void* q = nullptr;
+            HIPCHK(c, hipMalloc(&q, host.size() * sizeof(InstDev)));
+            c->allocs.push_back(q);
+            HIPCHK(c, hipMemcpy(q, host.data(), host.size() * sizeof(InstDev), hipMemcpyHostToDevice));
+            gr.dev = static_cast<InstDev*>(q);
+        }
+    }
+    {
+        std::vector<InstDev> host(c->inst.size());
+        for (size_t i = 0; i < c->inst.size(); ++i) host[i] = InstDev{c->inst[i].g, c->inst[i].b};
+        void* q = nullptr;
+        HIPCHK(c, hipMalloc(&q, host.size() * sizeof(InstDev)));
+        c->allocs.push_back(q);
+        HIPCHK(c, hipMemcpy(q, host.data(), host.size() * sizeof(InstDev), hipMemcpyHostToDevice));
+        for (size_t i = 0; i < c->inst.size(); ++i) c->inst[i].self = static_cast<InstDev*>(q) + i;
+    }
     for (auto& cl : c->classes) {
+        cl.g = c->inst[cl.members[0]].g;
         std::vector<InstDev> host(cl.members.size());
         for (size_t m = 0; m < cl.members.size(); ++m)
             host[m] = InstDev{c->inst[cl.members[m]].g, c->inst[cl.members[m]].b};
@@ -333,7 +395,6 @@ int build_classes(tc_ctx* c) {
         c->allocs.push_back(q);
         HIPCHK(c, hipMemcpy(q, host.data(), host.size() * sizeof(InstDev), hipMemcpyHostToDevice));
         cl.dev = static_cast<InstDev*>(q);
-        for (size_t m = 0; m < cl.members.size(); ++m) c->inst[cl.members[m]].self = cl.dev + m;
     }
     return TC_OK;
 }
@@ -345,15 +406,15 @@ void drop_graph(tc_ctx* c) {
 }
 
 // Capture one full step (3 substeps of every instance) into a graph on the
-// current stream.  Shape classes share no memory, so with several classes
-// each one is captured on a side stream forked from and joined back into the
-// current stream: the graph gets one independent branch per class and the
-// classes run concurrently on replay.  The captured work has no memset or
-// host callback nodes.
+// current stream.  A stage with several launch groups forks them onto side
+// streams and joins them back before the next stage (the groups of a stage
+// share no memory), so they run concurrently on replay.  The captured work
+// has no memset or host callback nodes.
 int capture_step(tc_ctx* c) {
     drop_graph(c);
-    const int ncl = (int)c->classes.size();
-    const int nbranch = ncl > 1 ? std::min(ncl, kMaxBranches) : 0;
+    int maxg = 1;
+    for (int st = 0; st < ST_COUNT; ++st) maxg = std::max(maxg, (int)c->groups[st].size());
+    const int nbranch = maxg > 1 ? std::min(maxg, kMaxBranches) : 0;
     while ((int)c->branch.size() < nbranch) {
         Branch br;
         if (hipStreamCreateWithFlags(&br.stream, hipStreamNonBlocking) != hipSuccess)
@@ -368,21 +429,27 @@ int capture_step(tc_ctx* c) {
     hipGraph_t graph = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int rc = TC_OK;
-    if (nbranch) {
-        hipError_t e = hipEventRecord(c->fork, c->stream);
-        for (int b = 0; b < nbranch && e == hipSuccess; ++b) e = hipStreamWaitEvent(c->branch[b].stream, c->fork, 0);
-        for (int ci = 0; ci < ncl && e == hipSuccess; ++ci)
-            for (int k = 0; k < 3; ++k) class_substep(c, c->classes[ci], k, c->branch[ci % nbranch].stream);
-        for (int b = 0; b < nbranch && e == hipSuccess; ++b) {
-            e = hipEventRecord(c->branch[b].done, c->branch[b].stream);
-            if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->branch[b].done, 0);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        for (int st = 0; st < ST_COUNT && e == hipSuccess; ++st) {
+            const auto& G = c->groups[st];
+            if (G.size() == 1 || nbranch == 0) {
+                for (const auto& gr : G) group_stage(c, st, gr, k, c->stream);
+                continue;
+            }
+            const int nb = std::min((int)G.size(), nbranch);
+            e = hipEventRecord(c->fork, c->stream);
+            for (int b = 0; b < nb && e == hipSuccess; ++b) e = hipStreamWaitEvent(c->branch[b].stream, c->fork, 0);
+            for (size_t q = 0; q < G.size() && e == hipSuccess; ++q) group_stage(c, st, G[q], k, c->branch[q % nb].stream);
+            for (int b = 0; b < nb && e == hipSuccess; ++b) {
+                e = hipEventRecord(c->branch[b].done, c->branch[b].stream);
+                if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->branch[b].done, 0);
+            }
         }
-        if (e != hipSuccess) rc = hip_fail(c, e, "graph branch fork/join");
-        else rc = check_launch(c, "substep launch");
-    } else {
-        for (int k = 0; k < 3 && rc == TC_OK; ++k) rc = run_substep(c, k);
     }
-    hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (e != hipSuccess) rc = hip_fail(c, e, "graph branch fork/join");
+    else rc = check_launch(c, "substep launch");
+    e = hipStreamEndCapture(c->stream, &graph);
     if (rc) {
         if (graph) (void)hipGraphDestroy(graph);
         return rc;
