@@ -272,19 +272,30 @@ int build_setup(const tc_geometry& g, Setup& s, std::string& err) {
     }
 
     // Segmented sweeps: the centred block (rows 2..nr-3) is cut into
-    // DV_SEGMENTS segments of dv_seg rows.  Inside segment [s0, s1) the
+    // dv_nseg segments of dv_seg rows (8 of 4, 8 or 16; 16 segments of 8
+    // rows measured slower).  Inside segment [s0, s1) the
     // forward recurrence y_n = r_n - l1_n y_{n-1} - l2_n y_{n-2} is the
     // particular solution from zero carry-in plus y_{s0-1} hf1 + y_{s0-2} hf2,
     // the backward one x_n = (y_n - u1_n x_{n+1} - u2_n x_{n+2}) / u0_n the
     // particular solution plus x_{s1} hb1 + x_{s1+1} hb2.
     {
         const int nc = nr - 4;
-        int L = 4;
-        while (DV_SEGMENTS * L < nc) L *= 2;
-        s.dv_seg = L <= 16 ? L : 0;
+        int L = 0, S = 0;
+        if (nc <= 32) {
+            L = 4;
+            S = 8;
+        } else if (nc <= 64) {
+            L = 8;
+            S = 8;
+        } else if (nc <= 128) {
+            L = 16;
+            S = 8;
+        }
+        s.dv_seg = L;
+        s.dv_nseg = S;
         s.dvh.assign((size_t)4 * nr, 0.0);
         if (s.dv_seg) {
-            for (int seg = 0; seg < DV_SEGMENTS; ++seg) {
+            for (int seg = 0; seg < S; ++seg) {
                 const int s0 = 2 + seg * L, s1 = std::min(s0 + L, nr - 2);
                 for (int which = 0; which < 2; ++which) {
                     ld a1 = which == 0 ? 1.0L : 0.0L, a2 = which == 0 ? 0.0L : 1.0L;  // y_{n-1}, y_{n-2}

@@ -35,13 +35,14 @@ struct Setup {
     // LU of the centred block (rows 2..nr-3) of d0, unpivoted, per row:
     // {l2, l1, 1/u0, u1, u2}
     std::vector<double> blu;          // [nr][5]
-    // Segmented sweeps of the same system (8 segments of dv_seg rows of the
-    // centred block; dv_seg = 0 when the block has more than 128 rows): the
+    // Segmented sweeps of the same system (dv_nseg segments of dv_seg rows of
+    // the centred block; dv_seg = 0 when the block has more than 128 rows): the
     // responses of the forward and backward recurrences inside each segment
     // to unit values carried in from the neighbouring segment,
     // [4][nr] = {forward from y_{s0-1}, forward from y_{s0-2},
     //            backward from x_{s1}, backward from x_{s1+1}}.
     int dv_seg = 0;
+    int dv_nseg = 0;
     std::vector<double> dvh;          // [4][nr]
     std::vector<double> m;            // [nj]   m_j
     std::vector<double> alpha;        // [nl]   alpha_l, l = -kz..kz
@@ -52,7 +53,6 @@ struct Setup {
     double c(int fam, int n, int j) const { return coef[(fam * nr + n) * 5 + j]; }
 };
 
-constexpr int DV_SEGMENTS = 8;  // segments of the centred block in the segmented D v sweeps
 
 // Validate g and fill s.  Returns TC_OK or TC_EINVAL with a message in err.
 int build_setup(const tc_geometry& g, Setup& s, std::string& err);

@@ -31,6 +31,7 @@ struct DevGeom {
     const double* blu;      // [nr][5]
     const double* dvh;      // [4][nr] segment responses of the d0 sweeps
     int dv_seg;             // rows per segment of the segmented D v kernel, 0: sequential kernel
+    int dv_nseg;            // segments of the segmented D v kernel
     int rhs_rr;             // rows per chunk of the RHS kernel
     const double* m;        // [nj]
     const double* alpha;    // [nl]

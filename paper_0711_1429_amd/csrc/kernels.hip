@@ -291,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_dv(const InstDev* __restrict__ I) {
 // goes the same way in the other direction.  v is read once (plus a 4-row
 // halo per segment), D v written once, and all rows of a mode are in flight
 // together.  The mean slot of v is zero, so it needs no branch.
-template <int L>
+template <int L, int DV_SEGMENTS>
 __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
@@ -1189,9 +1189,7 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve_lu(const InstDev* __restrict
 // segments and corrects its rows; the back substitution runs the same way
 // from the last segment down.  Every right-hand side, factor and output is
 // read or written once, and all rows of a column are in flight together.
-constexpr int SV_SEGMENTS = 8;
-
-template <int L>
+template <int L, int SV_SEGMENTS>
 __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* __restrict__ I, int k) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
@@ -1810,11 +1808,11 @@ int reduction_blocks(const DevGeom& g) {
 
 void launch_dv(const Batch& B, hipStream_t s) {
     const DevGeom& g = B.g;
-    const dim3 gseg((g.P + 63) / 64, 1, B.count), bseg(64 * DV_SEGMENTS);
-    switch (g.dv_seg) {
-        case 4: hipLaunchKernelGGL(k_dv_seg<4>, gseg, bseg, 0, s, B.inst); return;
-        case 8: hipLaunchKernelGGL(k_dv_seg<8>, gseg, bseg, 0, s, B.inst); return;
-        case 16: hipLaunchKernelGGL(k_dv_seg<16>, gseg, bseg, 0, s, B.inst); return;
+    const dim3 gseg((g.P + 63) / 64, 1, B.count);
+    switch (g.dv_nseg * 100 + g.dv_seg) {
+        case 804: hipLaunchKernelGGL((k_dv_seg<4, 8>), gseg, dim3(64 * 8), 0, s, B.inst); return;
+        case 808: hipLaunchKernelGGL((k_dv_seg<8, 8>), gseg, dim3(64 * 8), 0, s, B.inst); return;
+        case 816: hipLaunchKernelGGL((k_dv_seg<16, 8>), gseg, dim3(64 * 8), 0, s, B.inst); return;
     }
     dim3 grid((g.P + NT - 1) / NT, 1, B.count);
     hipLaunchKernelGGL(k_dv, grid, dim3(NT), 0, s, B.inst);
@@ -1884,7 +1882,7 @@ long long stage_key(int stage, const DevGeom& g) {
     // run-time-length transforms launch per exact shape
     const long long shape = (1LL << 40) | ((long long)g.nr << 24) | ((long long)g.ntheta << 12) | g.nz;
     switch (stage) {
-        case ST_DV: return g.dv_seg;
+        case ST_DV: return g.dv_nseg * 100 + g.dv_seg;
         case ST_ZINV:
         case ST_ZFWD: return (!g.generic_fft && lane_length(g.nz)) ? g.nz : shape;
         case ST_THETA: return (!g.generic_fft && lane_length(g.ntheta)) ? g.ntheta : shape;
@@ -1961,20 +1959,24 @@ void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, 
     hipLaunchKernelGGL(k_factor, grid, dim3(SOLVE_NT), 0, s, g, b, c, k);
 }
 
-// rows per segment of the segmented solve: SV_SEGMENTS * L >= nr - 2, L <= 16
+// Segments of the segmented solve: 8 segments of L rows (L = 4 or 8), or 16
+// segments of 8 rows for up to 128 unknowns (at most 123 VGPRs per lane);
+// 0 above that (sequential kernel).  Returns 100 * segments + L.
 int solve_segment_rows(int nr) {
-    int L = 4;
-    while (SV_SEGMENTS * L < nr - 2) L *= 2;
-    return L <= 16 ? L : 0;
+    const int nu = nr - 2;
+    if (nu <= 8 * 4) return 804;
+    if (nu <= 8 * 8) return 808;
+    if (nu <= 16 * 8) return 1608;
+    return 0;
 }
 
 void launch_solve(const Batch& B, int k, hipStream_t s) {
     // grid.y selects the equation, grid.z the instance
-    const dim3 gseg((B.g.P + 63) / 64, 2, B.count), bseg(64 * SV_SEGMENTS);
+    const dim3 gseg((B.g.P + 63) / 64, 2, B.count);
     switch (solve_segment_rows(B.g.nr)) {
-        case 4: hipLaunchKernelGGL(k_solve_seg<4>, gseg, bseg, 0, s, B.inst, k); return;
-        case 8: hipLaunchKernelGGL(k_solve_seg<8>, gseg, bseg, 0, s, B.inst, k); return;
-        case 16: hipLaunchKernelGGL(k_solve_seg<16>, gseg, bseg, 0, s, B.inst, k); return;
+        case 804: hipLaunchKernelGGL((k_solve_seg<4, 8>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
+        case 808: hipLaunchKernelGGL((k_solve_seg<8, 8>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
+        case 1608: hipLaunchKernelGGL((k_solve_seg<8, 16>), gseg, dim3(64 * 16), 0, s, B.inst, k); return;
     }
     dim3 grid((B.g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2, B.count);
     hipLaunchKernelGGL(k_solve_lu, grid, dim3(SOLVE_NT), 0, s, B.inst, k);

@@ -230,6 +230,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     if ((rc = upload(c, in, &g.blu, s.blu))) return rc;
     if ((rc = upload(c, in, &g.dvh, s.dvh))) return rc;
     g.dv_seg = s.dv_seg;
+    g.dv_nseg = s.dv_nseg;
     if ((rc = upload(c, in, &g.m, s.m))) return rc;
     if ((rc = upload(c, in, &g.alpha, s.alpha))) return rc;
     if ((rc = upload(c, in, &g.tw_theta, s.tw_theta))) return rc;
