@@ -1612,8 +1612,8 @@ __global__ __launch_bounds__(64 * THETA_NW) __attribute__((amdgpu_waves_per_eu(2
     lane::fft<T, N, +1, true>(mine, v, gl, twl, sync);
     product_out(0, u, u);
     product_out(1, u, v);
-    load(2, w);
     product_out(3, v, v);
+    load(2, w);  // after vv: loading it earlier keeps a fourth register set live
     lane::fft<T, N, +1, true>(mine, w, gl, twl, sync);
     product_out(2, u, w);
     product_out(4, v, w);
