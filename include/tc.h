@@ -55,6 +55,10 @@ enum {
 enum { TC_PREC_FP64 = 0, TC_PREC_MIXED = 1 };
 
 enum {
+    TC_FLAG_LINEAR = 1,      /* nonlinear terms off: the six products are zero, so
+                                the step integrates the linear (Stokes) equations
+                                of Sec. 2 about the current mean profiles, with
+                                every explicit viscous term kept (a test mode) */
     TC_FLAG_DRYRUN = 2,      /* validate and size only; allocate no device memory  */
     TC_FLAG_GENERIC_FFT = 4  /* use the run-time-length FFT kernels for every size
                                 (the compiled lengths 8..768 otherwise take the

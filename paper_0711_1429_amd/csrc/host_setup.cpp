@@ -119,7 +119,7 @@ int build_setup(const tc_geometry& g, Setup& s, std::string& err) {
     if (!(fin(g.lz) && g.lz >= 0.0)) e << "lz must be >= 0; ";
     if (!(fin(g.stretch) && g.stretch >= 0.0 && g.stretch <= 10.0)) e << "stretch must lie in [0, 10]; ";
     if (g.precision != TC_PREC_FP64 && g.precision != TC_PREC_MIXED) e << "unknown precision; ";
-    if (g.flags & ~(TC_FLAG_DRYRUN | TC_FLAG_GENERIC_FFT)) e << "unknown flags; ";
+    if (g.flags & ~(TC_FLAG_LINEAR | TC_FLAG_DRYRUN | TC_FLAG_GENERIC_FFT)) e << "unknown flags; ";
     if (e.str().empty()) {
         // the theta kernel keeps three rows of length ntheta in LDS (64 KiB per block)
         const size_t csize = g.precision == TC_PREC_MIXED ? 8 : 16;

@@ -42,6 +42,7 @@ struct DevGeom {
     const double* wr;       // [nr] trapezoid weight * r
     FftPlanDev plan_theta, plan_z;
     int generic_fft;        // 1: run-time-length FFT kernels even for compiled lengths
+    int linear;             // 1: no products (the transform stages are not launched)
 };
 
 // Coefficients of one substep of the low-storage RK3 / Crank--Nicolson

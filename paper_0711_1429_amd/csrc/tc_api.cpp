@@ -211,6 +211,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
         return d;
     };
     g.generic_fft = (s.g.flags & TC_FLAG_GENERIC_FFT) ? 1 : 0;
+    g.linear = (s.g.flags & TC_FLAG_LINEAR) ? 1 : 0;
     g.plan_theta = plan(s.plan_theta);
     g.plan_z = plan(s.plan_z);
 
@@ -255,6 +256,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     b.pb = raw;
     if ((rc = dev_alloc(c, in, &raw, 6 * S * cz))) return rc;
     b.ps = raw;
+    HIPCHK(c, hipMemset(b.ps, 0, 6 * S * cz));  // stays zero for TC_FLAG_LINEAR
     if ((rc = dev_alloc(c, in, &b.lu, (size_t)3 * 2 * 5 * s.nr * g.npairs))) return rc;
     if ((rc = dev_alloc(c, in, &b.fold, (size_t)3 * 2 * 2 * g.npairs))) return rc;
     if ((rc = dev_alloc(c, in, &b.mwall, (size_t)3 * 2 * s.nr))) return rc;
@@ -317,6 +319,7 @@ int products_only(tc_ctx* c, Instance& in) {
     hipStream_t s = c->stream;
     const Batch B = batch_of(in);
     launch_dv(B, s);
+    if (in.g.linear) return check_launch(c, "product launch");  // products stay zero
     launch_zinv(B, c->fp32, s);
     launch_theta(B, c->fp32, s);
     launch_zfwd(B, c->fp32, s);
@@ -347,6 +350,7 @@ int build_classes(tc_ctx* c) {
         auto& G = c->groups[st];
         for (int i = 0; i < (int)c->inst.size(); ++i) {
             const DevGeom& g = c->inst[i].g;
+            if (g.linear && (st == ST_ZINV || st == ST_THETA || st == ST_ZFWD)) continue;
             const long long key = stage_key(st, g);
             LaunchGroup* found = nullptr;
             for (auto& gr : G)

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(_HERE, "libtc.so")
 
 TC_OK, TC_EINVAL, TC_ENOMEM, TC_EDEVICE, TC_ENONFINITE, TC_ESHAPE = 0, -1, -2, -3, -4, -5
 TC_PREC_FP64, TC_PREC_MIXED = 0, 1
+TC_FLAG_LINEAR = 1
 TC_FLAG_DRYRUN = 2
 TC_FLAG_GENERIC_FFT = 4
 

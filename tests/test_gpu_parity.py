@@ -282,3 +282,71 @@ def test_batched_instances_equal_single_runs():
     v, e, um, wm = multi.get_fields(0)
     rv, re_, rum, rwm = orc.fields()
     assert rel_l2(v, rv) < TOL and rel_l2(e, re_) < TOL
+
+
+def test_linear_flag_matches_oracle_without_products():
+    """TC_FLAG_LINEAR: the step with the six products set to zero equals the
+    oracle's step with its products replaced by zeros (a mixed instance set:
+    one linear and one full instance of different shapes in one context)."""
+    from tests.helpers import abi_geometry, fields_for, oracle_geometry
+    from oracle import Oracle
+    w = workload("tc-small-fp64", amplitude=1e-2)
+    orc = Oracle(oracle_geometry(w))
+    orc.products = lambda u, v, ww: {k: np.zeros((orc.geo.nr, orc.disc.nj * orc.disc.nl), complex)
+                                     for k in ("uu", "uv", "uw", "vv", "vw", "ww")}
+    w2 = workload("tc-medium-fp64")
+    gpu = tcb.Solver([abi_geometry(w, flags=tcb.TC_FLAG_LINEAR), abi_geometry(w2)])
+    f = fields_for(w, orc.disc.r)
+    orc.load(*f)
+    gpu.load_fields(*f, inst=0)
+    orc2, one = pair(w2)
+    gpu.load_fields(*fields_for(w2, gpu.grid(1)), inst=1)
+    for s in range(3):
+        orc.step(1)
+        gpu.step(1)
+        v, e, um, wm = gpu.get_fields(0)
+        rv, re_, rum, rwm = orc.fields()
+        assert rel_l2(v, rv) < TOL and rel_l2(e, re_) < TOL and rel_l2(wm, rwm) < TOL, s
+    assert all(np.all(p == 0) for p in gpu.products(0).values())
+    one.step(3)
+    for x, y in zip(gpu.get_fields(1), one.get_fields()):
+        assert np.array_equal(x, y)
+
+
+def test_linear_flag_decays_at_the_stokes_eigenvalue():
+    """Without products the perturbation obeys the Stokes problem about the
+    (unadvected) mean flow: seeded with the least stable Stokes eigenvector of
+    the discrete operator (radius ratio 0.5, Re = 100, axial wavenumber pi,
+    m = 0), its energy decays at twice the eigenvalue, -0.20088 (a value the
+    eigenproblem fixes independently of the time integrator)."""
+    from scipy.linalg import eig
+    from oracle import Geometry, Oracle
+    from tests.test_oracle_dynamics import linear_operator
+    geo = Geometry(zeta=0.5, re=100.0, nr=33, ntheta=4, nz=4, dt=1e-2, lz=2.0)
+    orc = Oracle(geo)
+    A, B = linear_operator(orc, 0, 1, np.zeros(geo.nr))
+    lam, vec = eig(A, B)
+    ok = np.isfinite(lam) & (np.abs(lam) < 1e6)
+    k = np.argmax(np.where(ok, lam.real, -np.inf))
+    assert abs(lam[k].real + 0.20088) < 1e-4 and abs(lam[k].imag) < 1e-8
+    # at m = 0 without base flow v and eta decouple, and the least stable mode
+    # may be a pure eta mode: scale by the whole eigenvector
+    x = vec[:, k] * (1e-6 / np.max(np.abs(vec[:, k])))
+    nr, kz = geo.nr, orc.disc.kz
+    v = np.zeros((nr, orc.disc.nj, orc.disc.nl), dtype=complex)
+    e = np.zeros_like(v)
+    v[:, 0, kz + 1], e[:, 0, kz + 1] = x[:nr], x[nr:]
+    v[:, 0, kz - 1], e[:, 0, kz - 1] = np.conj(x[:nr]), np.conj(x[nr:])
+    v[[0, -1]] = 0
+    e[[0, -1]] = 0
+    from paper_0711_1429_amd.synth import couette_profile
+    wlam = couette_profile(orc.disc.r, 0.5, 1.0, 0.0)
+    gpu = tcb.Solver(tcb.make_geometry(zeta=0.5, re=100.0, nr=33, ntheta=4, nz=4, dt=1e-2, lz=2.0,
+                                       flags=tcb.TC_FLAG_LINEAR))
+    gpu.load_fields(v, e, np.zeros(geo.nr), wlam)
+    e0 = gpu.stats()["energy_pert"]
+    gpu.step(100)  # t = 1
+    e1 = gpu.stats()["energy_pert"]
+    sigma = np.log(e1 / e0) / 2.0
+    print(f"decay rate {sigma:.6f}, eigenvalue {lam[k].real:.6f}", flush=True)
+    assert abs(sigma / lam[k].real - 1) < 1e-4
