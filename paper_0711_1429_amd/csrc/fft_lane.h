@@ -214,14 +214,14 @@ __host__ __device__ constexpr int last_slot_to_m(int slot) {
 }
 
 // LDS address of transform element e.  For N >= 64 the low four bits of e
-// are XOR-ed with bits 2..5 (12 points per lane) or 3..6 (8 points per lane):
-// a bijection inside each aligned block of 16 elements that spreads the
-// strided stores of the Stockham passes over distinct LDS banks.
-template <int N>
+// are XOR-ed with bits 3..6: a bijection inside each aligned block of 16
+// elements that spreads the strided stores of the Stockham passes over
+// distinct LDS banks.  Complex floats of the 12-points-per-lane lengths are
+// stored in natural order instead, which measured faster for them.
+template <typename T, int N>
 __host__ __device__ __forceinline__ int swz(int e) {
-    if constexpr (N >= 64 && N % 16 == 0) {
-        constexpr int S = points_per_lane(N) == 12 ? 2 : 3;
-        return e ^ ((e >> S) & 15);
+    if constexpr (N >= 64 && N % 16 == 0 && !(sizeof(T) == 4 && points_per_lane(N) == 12)) {
+        return e ^ ((e >> 3) & 15);
     } else {
         return e;
     }
@@ -299,7 +299,7 @@ __host__ __device__ __forceinline__ void load_pass(const C<T>* buf, C<T>* x, int
 #pragma unroll
     for (int t = 0; t < K; ++t)
 #pragma unroll
-        for (int k = 0; k < R; ++k) x[t * R + k] = buf[swz<N>(g + t * TL + k * (N / R))];
+        for (int k = 0; k < R; ++k) x[t * R + k] = buf[swz<T, N>(g + t * TL + k * (N / R))];
 }
 
 // Write the outputs of pass PASS to the transform's LDS region (natural
@@ -316,13 +316,13 @@ __host__ __device__ __forceinline__ void store_pass(C<T>* buf, const C<T>* x, in
         const int jb = g + t * TL;
         const int idx = (jb / NS) * NS * R + jb % NS;
 #pragma unroll
-        for (int k = 0; k < R; ++k) buf[swz<N>(idx + k * NS)] = x[t * R + k];
+        for (int k = 0; k < R; ++k) buf[swz<T, N>(idx + k * NS)] = x[t * R + k];
     }
 }
 
 // Runs passes PASS.. with x holding the inputs of pass PASS.  When
 // OUT_REGS, the last pass's outputs stay in x (layout above); otherwise they
-// are written to buf, element e at swz<N>(e).  SYNC() is called between every LDS
+// are written to buf, element e at swz<T, N>(e).  SYNC() is called between every LDS
 // write and read (and between a read and the next overwrite of buf).
 template <typename T, int N, int PASS, int SIGN, bool OUT_REGS, typename Sync>
 __host__ __device__ __forceinline__ void run_passes(C<T>* buf, C<T>* x, int g, const C<T>* tw, const Sync& sync) {

@@ -1594,8 +1594,8 @@ __global__ __launch_bounds__(64 * THETA_NW) __attribute__((amdgpu_waves_per_eu(2
         if (active) {
             C<T>* out = pb + (((size_t)prod * nr + r) * nz + z0) * nj;
             for (int j = gl; j < nj; j += TL) {
-                const C<T> h = mine[lane::swz<N>(j)];
-                const C<T> hm = mine[lane::swz<N>(j == 0 ? 0 : N - j)];
+                const C<T> h = mine[lane::swz<T, N>(j)];
+                const C<T> hm = mine[lane::swz<T, N>(j == 0 ? 0 : N - j)];
                 out[j] = C<T>{(T)0.5 * (h.x + hm.x), (T)0.5 * (h.y - hm.y)};
                 out[nj + j] = C<T>{(T)0.5 * (h.y + hm.y), (T)0.5 * (hm.x - h.x)};
             }

@@ -48,7 +48,7 @@ double run_case(unsigned seed) {
     }
     for (auto& t : th) t.join();
     if (!OUT_REGS)
-        for (int k = 0; k < N; ++k) out[k] = buf[lane::swz<N>(k)];
+        for (int k = 0; k < N; ++k) out[k] = buf[lane::swz<double, N>(k)];
     double err = 0, scale = 0;
     for (int k = 0; k < N; ++k) {
         std::complex<long double> s = 0;
