@@ -57,8 +57,9 @@ struct StepCoef {
 struct DevBuf {
     C<double>* v;
     C<double>* eta;
-    C<double>* nv[2];    // explicit-term registers of v, alternating by substep (mean slot: mean axial)
-    C<double>* neta[2];  // the same for eta (mean slot: mean azimuthal)
+    void* nv[2];       // explicit-term registers of v, alternating by substep (mean slot:
+                       // mean axial); complex of the transform precision
+    void* neta[2];     // the same for eta (mean slot: mean azimuthal)
     C<double>* dv;     // radial derivative of v
     C<double>* rv;     // right-hand side / forward-elimination values of v
     C<double>* re;     // the same for eta

@@ -656,8 +656,8 @@ __device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, 
         }
         double pu = 0.0, pw = 0.0;
         if (K > 0) {
-            pu = b.nv[K - 1][gid].x;
-            pw = b.neta[K - 1][gid].x;
+            pu = (double)((const C<TP>*)b.nv[K - 1])[gid].x;
+            pw = (double)((const C<TP>*)b.neta[K - 1])[gid].x;
         }
         rv.x = iu + g.dt * (sc.gamma * fu + sc.rho * pu);
         re.x = iw + g.dt * (sc.gamma * fw + sc.rho * pw);
@@ -665,8 +665,8 @@ __device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, 
         fnw.x = fw;
     }
     if (K < 2) {
-        b.nv[K][gid] = fnu;
-        b.neta[K][gid] = fnw;
+        ((C<TP>*)b.nv[K])[gid] = C<TP>{(TP)fnu.x, (TP)0};
+        ((C<TP>*)b.neta[K])[gid] = C<TP>{(TP)fnw.x, (TP)0};
     }
     b.rv[gid] = rv;
     b.re[gid] = re;
@@ -771,28 +771,33 @@ __device__ __forceinline__ void rhs_acc_both(RhsAcc& A, const RhsOps& o, const d
     A.Nv = cfma(c0, o.nv0, cfma(c1, o.nv1, cfma(c2, o.nv2, cfma(c2s, o.nv2s, A.Nv))));
 }
 
+template <typename TP>
+__device__ __forceinline__ C<TP> narrow(cd z) { return C<TP>{(TP)z.x, (TP)z.y}; }
+template <typename TP>
+__device__ __forceinline__ cd widen(C<TP> z) { return cd{(double)z.x, (double)z.y}; }
+
 // right-hand side of one row: (M + beta dt nu L) q + dt (gamma N + rho N_prev)
-template <int K>
-__device__ __forceinline__ void rhs_store(cd* __restrict__ nv, cd* __restrict__ ne, cd* __restrict__ rv,
+template <typename TP, int K>
+__device__ __forceinline__ void rhs_store(C<TP>* __restrict__ nv, C<TP>* __restrict__ ne, cd* __restrict__ rv,
                                           cd* __restrict__ re, size_t gid, bool vrow, const RhsAcc& A, cd pv,
                                           cd pe, double dt, const StepCoef& sc) {
     cd r = {0, 0};
     if (vrow) r = cfma(dt * sc.gamma, A.Nv, K > 0 ? cfma(dt * sc.rho, pv, A.Iv) : A.Iv);
     const cd q = cfma(dt * sc.gamma, A.Ne, K > 0 ? cfma(dt * sc.rho, pe, A.Ie) : A.Ie);
     if (K < 2) {
-        nv[gid] = vrow ? A.Nv : cd{0, 0};
-        ne[gid] = A.Ne;
+        nv[gid] = narrow<TP>(vrow ? A.Nv : cd{0, 0});
+        ne[gid] = narrow<TP>(A.Ne);
     }
     rv[gid] = r;
     re[gid] = q;
 }
 
-template <int K>
-__device__ __forceinline__ void rhs_zero_row(cd* __restrict__ nv, cd* __restrict__ ne, cd* __restrict__ rv,
+template <typename TP, int K>
+__device__ __forceinline__ void rhs_zero_row(C<TP>* __restrict__ nv, C<TP>* __restrict__ ne, cd* __restrict__ rv,
                                              cd* __restrict__ re, size_t gid) {
     if (K < 2) {
-        nv[gid] = cd{0, 0};
-        ne[gid] = cd{0, 0};
+        nv[gid] = C<TP>{(TP)0, (TP)0};
+        ne[gid] = C<TP>{(TP)0, (TP)0};
     }
     rv[gid] = cd{0, 0};
     re[gid] = cd{0, 0};
@@ -819,8 +824,8 @@ __device__ __forceinline__ void pin_both(RhsAcc& A) {
 template <typename TP, int K>
 __device__ __forceinline__ void rhs_lane(const cd* __restrict__ v, const cd* __restrict__ eta,
                                          const cd* __restrict__ dv, const C<TP>* __restrict__ ps,
-                                         const cd* __restrict__ pnv, const cd* __restrict__ pne,
-                                         cd* __restrict__ nnv, cd* __restrict__ nne, cd* __restrict__ rv,
+                                         const C<TP>* __restrict__ pnv, const C<TP>* __restrict__ pne,
+                                         C<TP>* __restrict__ nnv, C<TP>* __restrict__ nne, cd* __restrict__ rv,
                                          cd* __restrict__ re, const double* __restrict__ coef,
                                          const double* __restrict__ r, int nr, int P, int mode, int n0, int rr,
                                          bool first, bool last, double mm, double al, double nu, double dt,
@@ -848,8 +853,8 @@ __device__ __forceinline__ void rhs_lane(const cd* __restrict__ v, const cd* __r
             cd npv = {0, 0}, npe = {0, 0};
             if (K > 0) {
                 const size_t gid = (size_t)max(n0 + mi - 3, 0) * P + mode;
-                npv = pnv[gid];
-                npe = pne[gid];
+                npv = widen<TP>(pnv[gid]);
+                npe = widen<TP>(pne[gid]);
             }
             const RhsOps o = rhs_ops<TP>(cur, r[m], mm, al, nu, bdt);
 #pragma unroll
@@ -871,7 +876,7 @@ __device__ __forceinline__ void rhs_lane(const cd* __restrict__ v, const cd* __r
                 pin_eta(W2);
             }
             if (q == 4 || base > 0)  // row mi - 4 is complete
-                rhs_store<K>(nnv, nne, rv, re, (size_t)(n0 + mi - 4) * P + mode, true, A[(q + 1) % 5], pv, pe, dt,
+                rhs_store<TP, K>(nnv, nne, rv, re, (size_t)(n0 + mi - 4) * P + mode, true, A[(q + 1) % 5], pv, pe, dt,
                              sc);
             pv = npv;
             pe = npe;
@@ -880,15 +885,15 @@ __device__ __forceinline__ void rhs_lane(const cd* __restrict__ v, const cd* __r
     }
     if (first) {
         cd p1 = {0, 0};
-        if (K > 0) p1 = pne[(size_t)P + mode];
-        rhs_store<K>(nnv, nne, rv, re, (size_t)P + mode, false, W1, cd{0, 0}, p1, dt, sc);
-        rhs_zero_row<K>(nnv, nne, rv, re, (size_t)mode);
+        if (K > 0) p1 = widen<TP>(pne[(size_t)P + mode]);
+        rhs_store<TP, K>(nnv, nne, rv, re, (size_t)P + mode, false, W1, cd{0, 0}, p1, dt, sc);
+        rhs_zero_row<TP, K>(nnv, nne, rv, re, (size_t)mode);
     }
     if (last) {
         cd p2 = {0, 0};
-        if (K > 0) p2 = pne[(size_t)(nr - 2) * P + mode];
-        rhs_store<K>(nnv, nne, rv, re, (size_t)(nr - 2) * P + mode, false, W2, cd{0, 0}, p2, dt, sc);
-        rhs_zero_row<K>(nnv, nne, rv, re, (size_t)(nr - 1) * P + mode);
+        if (K > 0) p2 = widen<TP>(pne[(size_t)(nr - 2) * P + mode]);
+        rhs_store<TP, K>(nnv, nne, rv, re, (size_t)(nr - 2) * P + mode, false, W2, cd{0, 0}, p2, dt, sc);
+        rhs_zero_row<TP, K>(nnv, nne, rv, re, (size_t)(nr - 1) * P + mode);
     }
 }
 
@@ -923,9 +928,11 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepC
     if (mode == g.mean) return;  // done by the blockIdx.y == 1 blocks
     const int j = mode / g.nl;
     const int li = mode - j * g.nl;
-    rhs_lane<TP, K>(b.v, b.eta, b.dv, ps, K > 0 ? b.nv[K > 0 ? K - 1 : 0] : nullptr,
-                    K > 0 ? b.neta[K > 0 ? K - 1 : 0] : nullptr, K < 2 ? b.nv[K < 2 ? K : 0] : nullptr,
-                    K < 2 ? b.neta[K < 2 ? K : 0] : nullptr, b.rv, b.re, g.coef, g.r, nr, P, mode, n0, rr, first,
+    using CT = C<TP>;
+    rhs_lane<TP, K>(b.v, b.eta, b.dv, ps, K > 0 ? (const CT*)b.nv[K > 0 ? K - 1 : 0] : nullptr,
+                    K > 0 ? (const CT*)b.neta[K > 0 ? K - 1 : 0] : nullptr,
+                    K < 2 ? (CT*)b.nv[K < 2 ? K : 0] : nullptr, K < 2 ? (CT*)b.neta[K < 2 ? K : 0] : nullptr,
+                    b.rv, b.re, g.coef, g.r, nr, P, mode, n0, rr, first,
                     last, g.m[j], g.alpha[li], g.nu, g.dt, sc);
 }
 
@@ -1526,7 +1533,9 @@ __host__ __device__ constexpr int m_to_last_slot(int m) {
     return 0;
 }
 
-constexpr int THETA_NW = 4;  // wavefronts per block of the theta kernel
+// wavefronts per block of the theta kernel (measured best: 4 in FP64, 2 in FP32)
+template <typename T>
+constexpr int theta_waves() { return sizeof(T) == 8 ? 4 : 2; }
 
 // theta rows: each wavefront owns W = 64 / TL packed row pairs (z0, z0 + 1)
 // and does everything for them.  It loads u, v and w, inverse-transforms them
@@ -1535,7 +1544,7 @@ constexpr int THETA_NW = 4;  // wavefronts per block of the theta kernel
 // forward-transforms it through its own LDS region.  The wavefronts of a
 // block share only the twiddle table, so no block-wide barrier follows it.
 template <typename T, int N>
-__global__ __launch_bounds__(64 * THETA_NW) __attribute__((amdgpu_waves_per_eu(2))) void k_theta_wave(
+__global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_per_eu(2))) void k_theta_wave(
     const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
@@ -1543,19 +1552,19 @@ __global__ __launch_bounds__(64 * THETA_NW) __attribute__((amdgpu_waves_per_eu(2
     C<T>* __restrict__ pb = (C<T>*)b.pb;
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
-    __shared__ C<T> lds[THETA_NW * W * N];
+    __shared__ C<T> lds[theta_waves<T>() * W * N];
     __shared__ C<T> twl[lane::tw_size<N>() + 1];  // per-pass twiddles
-    if ((int)blockIdx.y >= g.nr || (int)blockIdx.x * THETA_NW * W >= g.nz / 2) return;  // whole block
+    if ((int)blockIdx.y >= g.nr || (int)blockIdx.x * theta_waves<T>() * W >= g.nz / 2) return;  // whole block
     const int wv = threadIdx.x / 64;
     const int lw = threadIdx.x - wv * 64;
     const int grp = lw / TL;
     const int gl = lw - grp * TL;
-    const int rp = (blockIdx.x * THETA_NW + wv) * W + grp;
+    const int rp = (blockIdx.x * theta_waves<T>() + wv) * W + grp;
     const int nz = g.nz, kt = g.kt, nj = g.nj, nr = g.nr;
     const bool active = rp < nz / 2;
     const int r = blockIdx.y;
     const int z0 = 2 * rp;
-    lane::fill_twiddles<T, N>(twl, tw_t<T>(g), threadIdx.x, 64 * THETA_NW);
+    lane::fill_twiddles<T, N>(twl, tw_t<T>(g), threadIdx.x, 64 * theta_waves<T>());
     // the z-spectral rows of field fl packed into the complex sequence of the
     // two real rows (z0, z0 + 1)
     auto load = [&](int fl, C<T>* x) {
@@ -1834,9 +1843,9 @@ void zfwd_lane(const Batch& B, hipStream_t s) {
 }
 template <typename T, int N>
 void theta_lane(const Batch& B, hipStream_t s) {
-    constexpr int RB = (64 / lane::Plan<N>::TL) * THETA_NW;  // row pairs per block
+    constexpr int RB = (64 / lane::Plan<N>::TL) * theta_waves<T>();  // row pairs per block
     dim3 grid((B.g.nz / 2 + RB - 1) / RB, B.g.nr, B.count);
-    hipLaunchKernelGGL((k_theta_wave<T, N>), grid, dim3(64 * THETA_NW), 0, s, B.inst);
+    hipLaunchKernelGGL((k_theta_wave<T, N>), grid, dim3(64 * theta_waves<T>()), 0, s, B.inst);
 }
 
 template <typename T>

@@ -244,9 +244,18 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     const size_t Q = (size_t)s.nr * s.nz * s.nj;
     const size_t cz = c->fp32 ? sizeof(C<float>) : sizeof(C<double>);
     DevBuf& b = in.b;
-    C<double>** c128[] = {&b.v, &b.eta, &b.nv[0], &b.neta[0], &b.nv[1], &b.neta[1], &b.dv, &b.rv, &b.re};
+    C<double>** c128[] = {&b.v, &b.eta, &b.dv, &b.rv, &b.re};
     for (auto p : c128)
         if ((rc = dev_alloc(c, in, p, S))) return rc;
+    // the N registers hold the explicit terms of the previous substep at the
+    // precision of the products they are formed from
+    char* nreg = nullptr;
+    if ((rc = dev_alloc(c, in, &nreg, 4 * S * cz))) return rc;
+    HIPCHK(c, hipMemset(nreg, 0, 4 * S * cz));
+    for (int q = 0; q < 2; ++q) {
+        b.nv[q] = nreg + (size_t)(2 * q) * S * cz;
+        b.neta[q] = nreg + (size_t)(2 * q + 1) * S * cz;
+    }
     if ((rc = dev_alloc(c, in, &b.umean, s.nr))) return rc;
     if ((rc = dev_alloc(c, in, &b.wmean, s.nr))) return rc;
     char* raw = nullptr;
@@ -634,9 +643,10 @@ int tc_load_fields(tc_ctx* c, int inst, const double* v, const double* eta, cons
     HIPCHK(c, hipMemcpyAsync(in->b.eta, eta, S * 16, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(in->b.umean, um, in->s.nr * 8, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(in->b.wmean, wm, in->s.nr * 8, hipMemcpyHostToDevice, s));
+    const size_t cz = c->fp32 ? sizeof(C<float>) : sizeof(C<double>);
     for (int q = 0; q < 2; ++q) {
-        HIPCHK(c, hipMemsetAsync(in->b.nv[q], 0, S * 16, s));
-        HIPCHK(c, hipMemsetAsync(in->b.neta[q], 0, S * 16, s));
+        HIPCHK(c, hipMemsetAsync(in->b.nv[q], 0, S * cz, s));
+        HIPCHK(c, hipMemsetAsync(in->b.neta[q], 0, S * cz, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
     in->time = 0.0;
@@ -823,9 +833,9 @@ double tc_kernel_bytes(const tc_ctx* cc, int inst, int id) {
         case K_THETA: return 3.0 * t * Q + 6.0 * t * Q;       // read 3 fields; write 6 products
         case K_ZFWD: return 6.0 * t * Q + 6.0 * t * S;        // read 6; write 6 spectra
         case K_RHS:  // read v, eta, D v and 6 spectra, write the RHS of v and eta; the
-                     // N registers are read by substeps 2, 3 and written by 1, 2
-                     // (the average over a step is given)
-            return (48.0 + 6.0 * t + 32.0 * 2.0 / 3.0 + 32.0 * 2.0 / 3.0 + 32.0) * S;
+                     // N registers (2 complex of the transform precision) are read by
+                     // substeps 2, 3 and written by 1, 2 (the average over a step is given)
+            return (48.0 + 6.0 * t + 2.0 * t * 2.0 / 3.0 + 2.0 * t * 2.0 / 3.0 + 32.0) * S;
         case K_SOLVE:  // read RHS and the 5 LU fields of both equations, write v, eta
             return 32.0 * S + 80.0 * in->s.nr * in->s.nj * (in->s.kz + 1.0) + 32.0 * S;
         case K_ENERGY: return 48.0 * S;
