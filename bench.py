@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--precision", choices=("fp64", "mixed"), default=None,
                    help="default: fp64, or mixed for the batched workload")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--autotune", choices=("on", "off", "auto"), default="auto",
+                   help="time the launch variants before the run (auto: on for the batched workload)")
     p.add_argument("--eager", action="store_true",
                    help="launch every kernel from the host instead of replaying the step graph "
                         "(for profilers that see only host-launched kernels)")
@@ -206,6 +208,11 @@ def main():
     for i, w in enumerate(ws):
         solver.load_fields(*initial_fields(solver.grid(i), w["zeta"], w["ntheta"], w["nz"], w["amplitude"],
                                            w["seed"]), inst=i)
+    tuned = args.autotune == "on" or (args.autotune == "auto" and batched)
+    if tuned:
+        print("bench: autotune", file=sys.stderr, flush=True)
+        solver.autotune(5)
+    tuning = sorted({tuple(solver.tuning(i).items()) for i in range(len(ws))})
     print(f"bench: {args.workload} {precision} warmup {args.warmup}", file=sys.stderr, flush=True)
     solver.step(args.warmup)
 
@@ -288,6 +295,7 @@ def main():
         "substep_model": {"bytes": model, "ms_per_substep": t_sub * 1e3,
                           "GBs": model / t_sub / 1e9, "frac": model / t_sub / 1e9 / HBM_PEAK_GBS},
         "ms_per_step_events": elapsed_events / args.steps * 1e3,
+        "launch_tuning": {"autotuned": tuned, "choices": [dict(t) for t in tuning]},
         "kernels": per_kernel,
     }
     w = w0

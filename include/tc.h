@@ -190,6 +190,22 @@ int tc_stats(tc_ctx* ctx, int inst, tc_stats_t* out);
  * are always launched eagerly. */
 int tc_use_graphs(tc_ctx* ctx, int enable);
 
+/* Pick, by timing on the device, the launch parameters that do not change the
+ * method: the rows per chunk of the explicit-term kernel (21, 16, 11 or 6) and
+ * the segment shape of the radial solve (8 x 4, 8 x 8 or 16 x 8 rows), per
+ * launch group.  Runs one substep to fill the intermediates, times `repeats`
+ * launches (1..1000) of each candidate and restores the state, the N
+ * registers and the time exactly, so the fields are unchanged on return.
+ * Allocates a temporary copy of the state (freed before returning).  The
+ * step graph is recaptured on the next tc_step. */
+int tc_autotune(tc_ctx* ctx, int repeats);
+
+/* The launch parameters in use for instance `inst` (after tc_create, or
+ * after tc_autotune): rows per chunk of the explicit-term kernel, and the
+ * solve's segment shape as 100 * segments + rows per segment (0: one lane
+ * walks every row).  Either pointer may be NULL. */
+int tc_tuning(const tc_ctx* ctx, int inst, int* rhs_rows, int* solve_shape);
+
 /* Per-kernel timing with HIP events on the context's stream.
  * enable = 1 starts recording (and clears the totals), 0 stops.  While on,
  * every launch is bracketed by events; tc_kernel_times fills ms[i] with the

@@ -1896,7 +1896,7 @@ long long stage_key(int stage, const DevGeom& g) {
         case ST_ZFWD: return (!g.generic_fft && lane_length(g.nz)) ? g.nz : shape;
         case ST_THETA: return (!g.generic_fft && lane_length(g.ntheta)) ? g.ntheta : shape;
         case ST_RHS: return 0;
-        case ST_SOLVE: return solve_segment_rows(g.nr);
+        case ST_SOLVE: return g.solve_seg;
     }
     return shape;
 }
@@ -1979,10 +1979,15 @@ int solve_segment_rows(int nr) {
     return 0;
 }
 
+bool solve_shape_fits(int code, int nr) {
+    if (code != 804 && code != 808 && code != 1608) return false;
+    return (code / 100) * (code % 100) >= nr - 2;
+}
+
 void launch_solve(const Batch& B, int k, hipStream_t s) {
     // grid.y selects the equation, grid.z the instance
     const dim3 gseg((B.g.P + 63) / 64, 2, B.count);
-    switch (solve_segment_rows(B.g.nr)) {
+    switch (B.g.solve_seg) {
         case 804: hipLaunchKernelGGL((k_solve_seg<4, 8>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
         case 808: hipLaunchKernelGGL((k_solve_seg<8, 8>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
         case 1608: hipLaunchKernelGGL((k_solve_seg<8, 16>), gseg, dim3(64 * 16), 0, s, B.inst, k); return;

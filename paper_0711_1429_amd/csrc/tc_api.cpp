@@ -72,6 +72,7 @@ struct tc_ctx {
     hipEvent_t fork = nullptr;
     std::vector<ShapeClass> classes;
     std::vector<LaunchGroup> groups[ST_COUNT];
+    InstDev* all_dev = nullptr;         // descriptors of all instances, in order
     std::vector<void*> allocs;          // class arrays
     double* hflags = nullptr;           // pinned: one non-finite flag per instance
     bool use_graphs = true;
@@ -231,6 +232,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     if ((rc = upload(c, in, &g.blu, s.blu))) return rc;
     if ((rc = upload(c, in, &g.dvh, s.dvh))) return rc;
     g.dv_seg = s.dv_seg;
+    g.solve_seg = solve_segment_rows(s.nr);
     g.dv_nseg = s.dv_nseg;
     if ((rc = upload(c, in, &g.m, s.m))) return rc;
     if ((rc = upload(c, in, &g.alpha, s.alpha))) return rc;
@@ -335,6 +337,8 @@ int products_only(tc_ctx* c, Instance& in) {
     return check_launch(c, "product launch");
 }
 
+int upload_descriptors(tc_ctx* c);
+
 // Group instances by launch shape and upload the per-class instance arrays.
 int build_classes(tc_ctx* c) {
     for (int i = 0; i < (int)c->inst.size(); ++i) {
@@ -379,37 +383,43 @@ int build_classes(tc_ctx* c) {
             if (st == ST_THETA) m.nz = std::max(m.nz, g.nz);
             found->members.push_back(i);
         }
-        for (auto& gr : G) {
-            std::vector<InstDev> host(gr.members.size());
-            for (size_t q = 0; q < gr.members.size(); ++q)
-                host[q] = InstDev{c->inst[gr.members[q]].g, c->inst[gr.members[q]].b};
-            void* q = nullptr;
-            HIPCHK(c, hipMalloc(&q, host.size() * sizeof(InstDev)));
-            c->allocs.push_back(q);
-            HIPCHK(c, hipMemcpy(q, host.data(), host.size() * sizeof(InstDev), hipMemcpyHostToDevice));
-            gr.dev = static_cast<InstDev*>(q);
-        }
     }
-    {
-        std::vector<InstDev> host(c->inst.size());
-        for (size_t i = 0; i < c->inst.size(); ++i) host[i] = InstDev{c->inst[i].g, c->inst[i].b};
+    // device descriptor arrays: one per launch group, one per shape class, and
+    // one of all instances (the single-instance launches)
+    auto alloc_array = [&](size_t n, InstDev** out) -> int {
         void* q = nullptr;
-        HIPCHK(c, hipMalloc(&q, host.size() * sizeof(InstDev)));
+        if (hipMalloc(&q, n * sizeof(InstDev)) != hipSuccess) return fail(c, TC_ENOMEM, "hipMalloc of descriptors");
         c->allocs.push_back(q);
-        HIPCHK(c, hipMemcpy(q, host.data(), host.size() * sizeof(InstDev), hipMemcpyHostToDevice));
-        for (size_t i = 0; i < c->inst.size(); ++i) c->inst[i].self = static_cast<InstDev*>(q) + i;
-    }
+        *out = static_cast<InstDev*>(q);
+        return TC_OK;
+    };
+    for (int st = 0; st < ST_COUNT; ++st)
+        for (auto& gr : c->groups[st])
+            if (int rc = alloc_array(gr.members.size(), &gr.dev)) return rc;
+    for (auto& cl : c->classes)
+        if (int rc = alloc_array(cl.members.size(), &cl.dev)) return rc;
+    if (int rc = alloc_array(c->inst.size(), &c->all_dev)) return rc;
+    for (size_t i = 0; i < c->inst.size(); ++i) c->inst[i].self = c->all_dev + i;
+    return upload_descriptors(c);
+}
+
+// Copy every instance's current DevGeom/DevBuf into the device descriptor
+// arrays (after a change of a per-instance launch parameter).
+int upload_descriptors(tc_ctx* c) {
+    auto put = [&](const std::vector<int>& members, InstDev* dev) {
+        std::vector<InstDev> host(members.size());
+        for (size_t q = 0; q < members.size(); ++q) host[q] = InstDev{c->inst[members[q]].g, c->inst[members[q]].b};
+        return hipMemcpy(dev, host.data(), host.size() * sizeof(InstDev), hipMemcpyHostToDevice);
+    };
+    for (int st = 0; st < ST_COUNT; ++st)
+        for (auto& gr : c->groups[st]) HIPCHK(c, put(gr.members, gr.dev));
     for (auto& cl : c->classes) {
         cl.g = c->inst[cl.members[0]].g;
-        std::vector<InstDev> host(cl.members.size());
-        for (size_t m = 0; m < cl.members.size(); ++m)
-            host[m] = InstDev{c->inst[cl.members[m]].g, c->inst[cl.members[m]].b};
-        void* q = nullptr;
-        HIPCHK(c, hipMalloc(&q, host.size() * sizeof(InstDev)));
-        c->allocs.push_back(q);
-        HIPCHK(c, hipMemcpy(q, host.data(), host.size() * sizeof(InstDev), hipMemcpyHostToDevice));
-        cl.dev = static_cast<InstDev*>(q);
+        HIPCHK(c, put(cl.members, cl.dev));
     }
+    std::vector<int> all(c->inst.size());
+    for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+    HIPCHK(c, put(all, c->all_dev));
     return TC_OK;
 }
 
@@ -813,6 +823,145 @@ int tc_use_graphs(tc_ctx* c, int enable) {
     (void)hipStreamSynchronize(c->stream);
     c->use_graphs = enable != 0;
     drop_graph(c);
+    return TC_OK;
+}
+
+namespace {
+
+// Mean duration (ms) of `reps` launches of stage st for group gr, substep k.
+int time_stage(tc_ctx* c, int st, const LaunchGroup& gr, int k, int reps, hipEvent_t e0, hipEvent_t e1,
+               double* ms) {
+    const Batch B = batch_of(gr);
+    auto launch = [&] {
+        if (st == ST_RHS) launch_rhs(B, c->fp32, step_coef(k), k, c->stream);
+        else launch_solve(B, k, c->stream);
+    };
+    launch();  // warm
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) launch();
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    if (int rc = check_launch(c, "autotune launch")) return rc;
+    HIPCHK(c, hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    return TC_OK;
+}
+
+}  // namespace
+
+int tc_autotune(tc_ctx* c, int repeats) {
+    if (!c) return TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    if (repeats < 1 || repeats > 1000) return fail(c, TC_EINVAL, "repeats must be in [1, 1000]");
+    collect_timing(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    const bool was_timing = c->timing;
+    c->timing = false;
+    // snapshot the state and the N registers; the tuning runs one substep to
+    // fill every intermediate and then re-launches idempotent stages
+    std::vector<void*> snap;
+    auto cleanup = [&] {
+        for (void* p : snap) (void)hipFree(p);
+        c->timing = was_timing;
+    };
+    struct Copy {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    std::vector<Copy> saved;
+    const size_t cz = c->fp32 ? sizeof(C<float>) : sizeof(C<double>);
+    for (auto& in : c->inst) {
+        const size_t S = (size_t)in.s.nr * in.g.P;
+        const std::pair<void*, size_t> parts[] = {{in.b.v, S * 16}, {in.b.eta, S * 16},
+                                                  {in.b.umean, in.s.nr * 8ul}, {in.b.wmean, in.s.nr * 8ul},
+                                                  {in.b.nv[0], S * cz}, {in.b.neta[0], S * cz},
+                                                  {in.b.nv[1], S * cz}, {in.b.neta[1], S * cz}};
+        for (auto& pr : parts) {
+            void* q = nullptr;
+            if (hipMalloc(&q, pr.second) != hipSuccess) {
+                cleanup();
+                return fail(c, TC_ENOMEM, "autotune: no memory for the state snapshot");
+            }
+            snap.push_back(q);
+            saved.push_back(Copy{q, pr.first, pr.second});
+            if (hipMemcpyAsync(q, pr.first, pr.second, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+                cleanup();
+                return fail(c, TC_EDEVICE, "autotune: snapshot copy failed");
+            }
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = TC_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(c, TC_EDEVICE, "hipEventCreate");
+    const int k = 1;  // a substep that reads and writes the N registers
+    if (!rc) rc = run_substep(c, k);
+    // RHS rows per chunk, per launch group
+    for (auto& gr : c->groups[ST_RHS]) {
+        if (rc) break;
+        int best_rr = -1;
+        double best = 1e30;
+        for (int rr : {21, 16, 11, 6}) {
+            bool ok = true;
+            for (int i : gr.members) ok = ok && rr <= c->inst[i].g.nr - 4;
+            if (!ok) continue;
+            for (int i : gr.members) c->inst[i].g.rhs_rr = rr;
+            gr.g.rhs_rr = rr;
+            if ((rc = upload_descriptors(c))) break;
+            double ms = 0;
+            if ((rc = time_stage(c, ST_RHS, gr, k, repeats, e0, e1, &ms))) break;
+            if (ms < best) {
+                best = ms;
+                best_rr = rr;
+            }
+        }
+        if (rc) break;
+        if (best_rr > 0) {
+            for (int i : gr.members) c->inst[i].g.rhs_rr = best_rr;
+            gr.g.rhs_rr = best_rr;
+        }
+        // groups whose members are too short for every candidate keep their rows
+        for (int i : gr.members) gr.g.rhs_rr = std::min(gr.g.rhs_rr, c->inst[i].g.rhs_rr);
+    }
+    // segment shape of the radial solve, per launch group
+    for (auto& gr : c->groups[ST_SOLVE]) {
+        if (rc || gr.g.solve_seg == 0) continue;
+        int best_code = gr.g.solve_seg;
+        double best = 1e30;
+        for (int code : {804, 808, 1608}) {
+            if (!solve_shape_fits(code, gr.g.nr)) continue;
+            gr.g.solve_seg = code;
+            double ms = 0;
+            if ((rc = time_stage(c, ST_SOLVE, gr, k, repeats, e0, e1, &ms))) break;
+            if (ms < best) {
+                best = ms;
+                best_code = code;
+            }
+        }
+        gr.g.solve_seg = best_code;
+        for (int i : gr.members) c->inst[i].g.solve_seg = best_code;
+    }
+    if (!rc) rc = upload_descriptors(c);
+    // restore the state
+    for (auto& cp : saved)
+        if (!rc && hipMemcpyAsync(const_cast<void*>(cp.src), cp.dst, cp.bytes, hipMemcpyDeviceToDevice, c->stream) !=
+                       hipSuccess)
+            rc = fail(c, TC_EDEVICE, "autotune: restore copy failed");
+    if (hipStreamSynchronize(c->stream) != hipSuccess && !rc) rc = fail(c, TC_EDEVICE, "autotune: synchronise");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    cleanup();
+    return rc;
+}
+
+int tc_tuning(const tc_ctx* cc, int inst, int* rhs_rows_out, int* solve_shape_out) {
+    tc_ctx* c = const_cast<tc_ctx*>(cc);
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (rhs_rows_out) *rhs_rows_out = in->g.rhs_rr;
+    if (solve_shape_out) *solve_shape_out = in->g.solve_seg;
     return TC_OK;
 }
 

@@ -78,6 +78,8 @@ _SIGNATURES = {
     "tc_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TcStats)]),
     "tc_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "tc_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
+    "tc_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "tc_kernel_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
     "tc_kernel_count": (ctypes.c_int, []),
     "tc_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -221,6 +223,14 @@ class Solver:
 
     def use_graphs(self, enable):
         self._check(self.lib.tc_use_graphs(self.ctx, int(bool(enable))))
+
+    def autotune(self, repeats=5):
+        self._check(self.lib.tc_autotune(self.ctx, int(repeats)))
+
+    def tuning(self, inst=0):
+        rr, sh = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.tc_tuning(self.ctx, inst, ctypes.byref(rr), ctypes.byref(sh)))
+        return {"rhs_rows": rr.value, "solve_shape": sh.value}
 
     def timing(self, enable):
         self._check(self.lib.tc_timing(self.ctx, int(bool(enable))))

@@ -350,3 +350,39 @@ def test_linear_flag_decays_at_the_stokes_eigenvalue():
     sigma = np.log(e1 / e0) / 2.0
     print(f"decay rate {sigma:.6f}, eigenvalue {lam[k].real:.6f}", flush=True)
     assert abs(sigma / lam[k].real - 1) < 1e-4
+
+
+def test_autotune_keeps_the_state_and_the_results():
+    """tc_autotune times launch variants that do not change the method: the
+    state is bit-identical afterwards, the chosen parameters are valid, and the
+    following steps still match the oracle."""
+    from paper_0711_1429_amd.synth import batched_instances
+    from tests.helpers import abi_geometry, fields_for
+    w = workload("tc-medium-fp64")
+    orc, gpu = pair(w)
+    before = gpu.get_fields()
+    gpu.autotune(2)
+    for x, y in zip(gpu.get_fields(), before):
+        assert np.array_equal(x, y)
+    t = gpu.tuning()
+    assert t["rhs_rows"] in (6, 11, 16, 21) and t["solve_shape"] in (804, 808, 1608)
+    orc.step(2)
+    gpu.step(2)
+    _compare_state(orc, gpu, label="after autotune")
+    # a batched context keeps its per-instance results as well
+    ws = batched_instances(64)[:5]
+    multi = tcb.Solver([abi_geometry(x, tcb.TC_PREC_MIXED) for x in ws])
+    for i, x in enumerate(ws):
+        multi.load_fields(*fields_for(x, multi.grid(i)), inst=i)
+    ref = tcb.Solver([abi_geometry(x, tcb.TC_PREC_MIXED) for x in ws])
+    for i, x in enumerate(ws):
+        ref.load_fields(*fields_for(x, ref.grid(i)), inst=i)
+    multi.autotune(2)
+    multi.step(2)
+    ref.step(2)
+    for i in range(len(ws)):
+        for x, y in zip(multi.get_fields(i), ref.get_fields(i)):
+            if multi.tuning(i)["solve_shape"] == ref.tuning(i)["solve_shape"]:
+                assert np.array_equal(x, y), i
+            else:  # another segmentation of the same solve: equal to rounding
+                assert rel_l2(np.atleast_1d(x), np.atleast_1d(y)) < 1e-12, i
