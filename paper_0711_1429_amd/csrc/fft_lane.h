@@ -243,8 +243,8 @@ template <int N>
 constexpr int tw_size() { return tw_offset(N, Plan<N>::NPASS); }
 
 // Fill the per-pass table from a full table of exp(+2 pi i e / N) (2N reals).
-template <typename T, int N, int PASS>
-__host__ __device__ __forceinline__ void fill_pass(C<T>* twp, const T* tw_full, int tid, int nthreads) {
+template <typename T, int N, int PASS, typename TwPtr>
+__host__ __device__ __forceinline__ void fill_pass(C<T>* twp, TwPtr tw_full, int tid, int nthreads) {
     if constexpr (PASS < Plan<N>::NPASS) {
         constexpr int NS = ns_before(N, PASS);
         constexpr int STEP = N / (NS * radices(N).r[PASS]);
@@ -257,8 +257,9 @@ __host__ __device__ __forceinline__ void fill_pass(C<T>* twp, const T* tw_full, 
     }
 }
 
-template <typename T, int N>
-__host__ __device__ __forceinline__ void fill_twiddles(C<T>* twp, const T* tw_full, int tid, int nthreads) {
+// tw_full: any pointer-like to T (a device kernel passes a global-address-space pointer)
+template <typename T, int N, typename TwPtr>
+__host__ __device__ __forceinline__ void fill_twiddles(C<T>* twp, TwPtr tw_full, int tid, int nthreads) {
     fill_pass<T, N, 1>(twp, tw_full, tid, nthreads);
 }
 

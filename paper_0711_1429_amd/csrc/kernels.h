@@ -12,6 +12,24 @@ struct C {
     T x, y;
 };
 
+// The same pointer in the global address space.  Every buffer the kernels
+// touch outside LDS is global memory, but pointers read from the instance
+// descriptors are generic, and loads and stores through generic pointers
+// compile to flat instructions, which count against the LDS wait counter as
+// well and so make every LDS wait also wait for outstanding memory traffic.
+// (The host pass, which only parses device code, keeps the generic pointer.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+#else
+template <typename T>
+__device__ __forceinline__ T* glb(T* p) {
+    return p;
+}
+#endif
+
 struct FftPlanDev {
     int n;
     int npass;

@@ -1548,8 +1548,8 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
     const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
-    const C<T>* __restrict__ zb = (const C<T>*)b.zb;
-    C<T>* __restrict__ pb = (C<T>*)b.pb;
+    const auto* __restrict__ zb = glb((const C<T>*)b.zb);
+    auto* __restrict__ pb = glb((C<T>*)b.pb);
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
     __shared__ C<T> lds[theta_waves<T>() * W * N];
@@ -1560,29 +1560,34 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
     const int grp = lw / TL;
     const int gl = lw - grp * TL;
     const int rp = (blockIdx.x * theta_waves<T>() + wv) * W + grp;
-    const int nz = g.nz, kt = g.kt, nj = g.nj, nr = g.nr;
+    const int nz = g.nz, nr = g.nr;
     const bool active = rp < nz / 2;
     const int r = blockIdx.y;
     const int z0 = 2 * rp;
-    lane::fill_twiddles<T, N>(twl, tw_t<T>(g), threadIdx.x, 64 * theta_waves<T>());
+    lane::fill_twiddles<T, N>(twl, glb(tw_t<T>(g)), threadIdx.x, 64 * theta_waves<T>());
     // the z-spectral rows of field fl packed into the complex sequence of the
-    // two real rows (z0, z0 + 1)
+    // two real rows (z0, z0 + 1).  K_theta = (N - 1) / 3 is fixed by N, so
+    // which of the kept band, the zero band and the mirrored band a register
+    // slot covers is known at compile time for every slot but one or two.
+    constexpr int KT = (N - 1) / 3, NJ = KT + 1;
     auto load = [&](int fl, C<T>* x) {
-        const C<T>* row0 = zb + (((size_t)fl * nr + r) * nz + z0) * nj;
-        const C<T>* row1 = row0 + nj;
+        const auto* row0 = zb + (((size_t)fl * nr + r) * nz + z0) * NJ;
+        const auto* row1 = row0 + NJ;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int p = gl + k * TL;
+            const bool low_all = k * TL + TL - 1 <= KT, low_none = k * TL > KT;
+            const bool high_all = k * TL >= N - KT, high_none = k * TL + TL - 1 < N - KT;
             C<T> h = {(T)0, (T)0};
             if (active) {
-                if (p <= kt) {
+                if (low_all || (!low_none && p <= KT)) {
                     C<T> a = row0[p], c = row1[p];
-                    if (p == 0) {
+                    if (k == 0 && p == 0) {
                         a.y = (T)0;
                         c.y = (T)0;
                     }
                     h = C<T>{a.x - c.y, a.y + c.x};
-                } else if (p >= N - kt) {
+                } else if (high_all || (!high_none && p >= N - KT)) {
                     const C<T> a = row0[N - p], c = row1[N - p];
                     h = C<T>{a.x + c.y, c.x - a.y};
                 }
@@ -1601,12 +1606,16 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
         lane::fft<T, N, -1, false>(mine, x, gl, twl, sync);
         sync();
         if (active) {
-            C<T>* out = pb + (((size_t)prod * nr + r) * nz + z0) * nj;
-            for (int j = gl; j < nj; j += TL) {
-                const C<T> h = mine[lane::swz<T, N>(j)];
-                const C<T> hm = mine[lane::swz<T, N>(j == 0 ? 0 : N - j)];
-                out[j] = C<T>{(T)0.5 * (h.x + hm.x), (T)0.5 * (h.y - hm.y)};
-                out[nj + j] = C<T>{(T)0.5 * (h.y + hm.y), (T)0.5 * (hm.x - h.x)};
+            auto* out = pb + (((size_t)prod * nr + r) * nz + z0) * NJ;
+#pragma unroll
+            for (int q = 0; q < (NJ + TL - 1) / TL; ++q) {
+                const int j = gl + q * TL;
+                if ((q + 1) * TL <= NJ || j < NJ) {
+                    const C<T> h = mine[lane::swz<T, N>(j)];
+                    const C<T> hm = mine[lane::swz<T, N>(j == 0 ? 0 : N - j)];
+                    out[j] = C<T>{(T)0.5 * (h.x + hm.x), (T)0.5 * (h.y - hm.y)};
+                    out[NJ + j] = C<T>{(T)0.5 * (h.y + hm.y), (T)0.5 * (hm.x - h.x)};
+                }
             }
         }
         sync();
@@ -1635,12 +1644,12 @@ template <typename T, int N>
 __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane(const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
-    const cd* __restrict__ v = b.v;
-    const cd* __restrict__ eta = b.eta;
-    const cd* __restrict__ dv = b.dv;
-    const double* __restrict__ umean = b.umean;
-    const double* __restrict__ wmean = b.wmean;
-    C<T>* __restrict__ zb = (C<T>*)b.zb;
+    const auto* __restrict__ v = glb(b.v);
+    const auto* __restrict__ eta = glb(b.eta);
+    const auto* __restrict__ dv = glb(b.dv);
+    const auto* __restrict__ umean = glb(b.umean);
+    const auto* __restrict__ wmean = glb(b.wmean);
+    auto* __restrict__ zb = glb((C<T>*)b.zb);
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL, PITCH = zlane_pitch(N);
     __shared__ C<T> lds[JB * PITCH];
@@ -1653,9 +1662,9 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     const int ncols = min(JB, nj - j0);
     const int j = j0 + c;
     const bool active = c < ncols;
-    const double R = g.r[r];
+    const double R = glb(g.r)[r];
     const size_t Pm = g.P;
-    const T* tw = tw_z<T>(g);
+    const auto* tw = glb(tw_z<T>(g));
     // a column's transform lives in TL lanes of one wavefront, so its LDS
     // exchanges need only wavefront-scope ordering; the block barriers below
     // guard the twiddle table and the transposed write-out, which cross columns
@@ -1663,7 +1672,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     __shared__ C<T> twl[lane::tw_size<N>() + 1];
     lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
     C<T> X[3][P];
-    const double mm = active ? g.m[j] : 0.0;
+    const double mm = active ? glb(g.m)[j] : 0.0;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         const int q = gl + k * TL;
@@ -1675,7 +1684,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
                 xu.x = (T)umean[r];
                 xw.x = (T)wmean[r];
             } else {
-                const double al = g.alpha[l + kz];
+                const double al = glb(g.alpha)[l + kz];
                 const double a = R * R / (al * al * R * R + mm * mm);
                 const cd vv = v[e];
                 cd u, w;
@@ -1696,7 +1705,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
 #pragma unroll
         for (int q = 0; q < P; ++q) lds[c * PITCH + gl + TL * lane::last_slot_to_m<N>(q)] = X[f][q];
         __syncthreads();
-        C<T>* out = zb + ((size_t)f * g.nr + r) * N * nj;
+        auto* out = zb + ((size_t)f * g.nr + r) * N * nj;
         for (int idx = threadIdx.x; idx < ncols * N; idx += NTH) {
             const int z = idx / ncols;
             const int cc = idx - z * ncols;
@@ -1712,8 +1721,8 @@ template <typename T, int N>
 __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane(const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
-    const C<T>* __restrict__ pb = (const C<T>*)b.pb;
-    C<T>* __restrict__ ps = (C<T>*)b.ps;
+    const auto* __restrict__ pb = glb((const C<T>*)b.pb);
+    auto* __restrict__ ps = glb((C<T>*)b.ps);
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL, PITCH = zlane_pitch(N);
     __shared__ C<T> lds[JB * PITCH];
@@ -1727,7 +1736,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
     const bool active = c < ncols;
     const size_t Pm = g.P;
     const T scale = (T)(1.0 / ((double)g.ntheta * (double)N));
-    const T* tw = tw_z<T>(g);
+    const auto* tw = glb(tw_z<T>(g));
     // as in k_zinv_lane: wavefront-scope ordering inside a column's transform,
     // block barriers around the transposed load, which crosses columns
     const WaveSync sync;
@@ -1737,13 +1746,17 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
     // while the current one is transformed
     C<T> nxt[P];
     auto fetch = [&](int f) {
-        const C<T>* in = pb + ((size_t)f * g.nr + r) * N * nj;
+        const auto* in = pb + ((size_t)f * g.nr + r) * N * nj;
 #pragma unroll
         for (int e = 0; e < P; ++e) {
             const int idx = threadIdx.x + e * NTH;
             const int z = idx / ncols;
             const int cc = idx - z * ncols;
-            nxt[e] = idx < ncols * N ? in[(size_t)z * nj + j0 + cc] : C<T>{(T)0, (T)0};
+            // past the tile the load repeats the plane's first element (in
+            // bounds) and its value is dropped
+            const bool ok = idx < ncols * N;
+            const C<T> t = in[ok ? (size_t)z * nj + j0 + cc : 0];
+            nxt[e] = ok ? t : C<T>{(T)0, (T)0};
         }
     };
     fetch(0);
@@ -1764,7 +1777,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
         sync();
         lane::fft<T, N, -1, true>(lds + c * PITCH, x, gl, twl, sync);
         if (active) {
-            C<T>* out = ps + (size_t)f * g.nr * Pm + (size_t)r * Pm + (size_t)(j0 + c) * nl;
+            auto* out = ps + (size_t)f * g.nr * Pm + (size_t)r * Pm + (size_t)(j0 + c) * nl;
 #pragma unroll
             for (int s = 0; s < P; ++s) {
                 const int q = gl + TL * lane::last_slot_to_m<N>(s);
@@ -1868,6 +1881,8 @@ bool zfwd_fast(const Batch& B, hipStream_t s) {
 }
 template <typename T>
 bool theta_fast(const Batch& B, hipStream_t s) {
+    // the lane kernel takes K_theta = (ntheta - 1) / 3 as a compile-time constant
+    if (B.g.kt != (B.g.ntheta - 1) / 3 || B.g.nj != B.g.kt + 1) return false;
     switch (B.g.ntheta) {
 #define TC_CASE(N) case N: theta_lane<T, N>(B, s); return true;
         TC_LANE_SIZES(TC_CASE)
