@@ -17,18 +17,29 @@ struct C {
 // descriptors are generic, and loads and stores through generic pointers
 // compile to flat instructions, which count against the LDS wait counter as
 // well and so make every LDS wait also wait for outstanding memory traffic.
-// (The host pass, which only parses device code, keeps the generic pointer.)
+// TC_GLOBAL qualifies such pointers in signatures.  (The host pass, which
+// only parses device code, keeps generic pointers.)
 #if defined(__HIP_DEVICE_COMPILE__)
-template <typename T>
-__device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
-    return (__attribute__((address_space(1))) T*)p;
-}
+#define TC_GLOBAL __attribute__((address_space(1)))
 #else
-template <typename T>
-__device__ __forceinline__ T* glb(T* p) {
-    return p;
-}
+#define TC_GLOBAL
 #endif
+template <typename T>
+__device__ __forceinline__ TC_GLOBAL T* glb(T* p) {
+    return (TC_GLOBAL T*)p;
+}
+
+// A table that no kernel writes, in the constant address space: reads of it
+// at wave-uniform addresses compile to scalar loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TC_CONST __attribute__((address_space(4)))
+#else
+#define TC_CONST
+#endif
+template <typename T>
+__device__ __forceinline__ const TC_CONST T* cst(const T* p) {
+    return (const TC_CONST T*)p;
+}
 
 struct FftPlanDev {
     int n;

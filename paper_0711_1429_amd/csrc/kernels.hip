@@ -295,8 +295,8 @@ template <int L, int DV_SEGMENTS>
 __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
-    const cd* __restrict__ v = b.v;
-    cd* __restrict__ dv = b.dv;
+    const auto* __restrict__ v = glb(b.v);
+    auto* __restrict__ dv = glb(b.dv);
     __shared__ cd xc[DV_SEGMENTS][2][64];
     if ((int)blockIdx.x * 64 >= g.P) return;  // past this instance's modes (whole block)
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -308,13 +308,13 @@ __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __re
     const size_t mode = act ? m0 : g.P - 1;  // idle lanes read a valid column
     const int s0 = 2 + seg * L;
     const int len = max(0, min(s0 + L, nr - 2) - s0);
-    const double* __restrict__ d0 = g.coef;
-    const double* __restrict__ d1 = g.coef + (size_t)nr * 5;
-    const double* __restrict__ blu = g.blu;
-    const double* __restrict__ hf1 = g.dvh;
-    const double* __restrict__ hf2 = g.dvh + nr;
-    const double* __restrict__ hb1 = g.dvh + 2 * nr;
-    const double* __restrict__ hb2 = g.dvh + 3 * nr;
+    const auto* __restrict__ d0 = glb(g.coef);
+    const auto* __restrict__ d1 = glb(g.coef) + (size_t)nr * 5;
+    const auto* __restrict__ blu = glb(g.blu);
+    const auto* __restrict__ hf1 = glb(g.dvh);
+    const auto* __restrict__ hf2 = glb(g.dvh) + nr;
+    const auto* __restrict__ hb1 = glb(g.dvh) + 2 * nr;
+    const auto* __restrict__ hb2 = glb(g.dvh) + 3 * nr;
     cd p[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) p[i] = cd{0, 0};
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __re
         for (int i = 0; i < L; ++i) {
             const int n = s0 + i;
             if (i < len) {
-                const double* k1 = d1 + (size_t)n * 5;
+                const auto* k1 = d1 + (size_t)n * 5;
                 cd rhs = cfma(k1[0], w[i], cfma(k1[1], w[i + 1], cfma(k1[2], w[i + 2],
                          cfma(k1[3], w[i + 3], cfma(k1[4], w[i + 4], cd{0, 0})))));
                 // the known D v at rows 1 and nr-2 move to the right-hand side
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __re
 #pragma unroll
         for (int i = L - 1; i >= 0; --i) {
             if (i < len) {
-                const double* o = blu + (size_t)(s0 + i) * 5;
+                const auto* o = blu + (size_t)(s0 + i) * 5;
                 const cd t = cfma(-o[4], q2, cfma(-o[3], q1, p[i]));
                 const cd q = {t.x * o[2], t.y * o[2]};
                 p[i] = q;
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(NT) void k_zfwd(const InstDev* __restrict__ I, int 
 
 // ---------------------------------------------------------------- k_rhs
 template <typename TP>
-__device__ __forceinline__ cd ldp(const C<TP>* p, size_t i) {
+__device__ __forceinline__ cd ldp(const TC_GLOBAL C<TP>* p, size_t i) {
     const C<TP> x = p[i];
     return cd{(double)x.x, (double)x.y};
 }
@@ -627,7 +627,7 @@ __device__ __forceinline__ cd ldp(const C<TP>* p, size_t i) {
 
 // mean (0,0) mode: mean axial and azimuthal momentum, one row
 template <typename TP, int K>
-__device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, const C<TP>* __restrict__ ps,
+__device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, const TC_GLOBAL C<TP>* __restrict__ ps,
                                              const StepCoef& sc, int n) {
     const size_t P = g.P;
     const int nr = g.nr;
@@ -679,8 +679,9 @@ struct RhsPoint {
 };
 
 template <typename TP>
-__device__ __forceinline__ void rhs_load(const cd* __restrict__ v, const cd* __restrict__ eta,
-                                         const cd* __restrict__ dv, const C<TP>* __restrict__ ps, size_t S, size_t e,
+__device__ __forceinline__ void rhs_load(const TC_GLOBAL cd* __restrict__ v, const TC_GLOBAL cd* __restrict__ eta,
+                                         const TC_GLOBAL cd* __restrict__ dv, const TC_GLOBAL C<TP>* __restrict__ ps,
+                                         size_t S, size_t e,
                                          RhsPoint<TP>& p) {
     p.v = v[e];
     p.eta = eta[e];
@@ -757,13 +758,15 @@ struct RhsAcc {
 };
 
 // eta row: co points at the coefficient of stencil point jj of the row
-__device__ __forceinline__ void rhs_acc_eta(RhsAcc& A, const RhsOps& o, const double* co, size_t fs, double bdt) {
+__device__ __forceinline__ void rhs_acc_eta(RhsAcc& A, const RhsOps& o, const TC_CONST double* co, size_t fs,
+                                            double bdt) {
     const double c0 = co[0], c1 = co[fs], c2s = co[3 * fs];
     A.Ie = cfma(c0 * o.ke0 + c2s * bdt, o.eta, A.Ie);
     A.Ne = cfma(c0, o.ne0, cfma(c1, o.ne1, A.Ne));
 }
 
-__device__ __forceinline__ void rhs_acc_both(RhsAcc& A, const RhsOps& o, const double* co, size_t fs, double bdt) {
+__device__ __forceinline__ void rhs_acc_both(RhsAcc& A, const RhsOps& o, const TC_CONST double* co, size_t fs,
+                                             double bdt) {
     const double c0 = co[0], c1 = co[fs], c2 = co[2 * fs], c2s = co[3 * fs], c4s = co[4 * fs];
     A.Ie = cfma(c0 * o.ke0 + c2s * bdt, o.eta, A.Ie);
     A.Ne = cfma(c0, o.ne0, cfma(c1, o.ne1, A.Ne));
@@ -778,8 +781,8 @@ __device__ __forceinline__ cd widen(C<TP> z) { return cd{(double)z.x, (double)z.
 
 // right-hand side of one row: (M + beta dt nu L) q + dt (gamma N + rho N_prev)
 template <typename TP, int K>
-__device__ __forceinline__ void rhs_store(C<TP>* __restrict__ nv, C<TP>* __restrict__ ne, cd* __restrict__ rv,
-                                          cd* __restrict__ re, size_t gid, bool vrow, const RhsAcc& A, cd pv,
+__device__ __forceinline__ void rhs_store(TC_GLOBAL C<TP>* __restrict__ nv, TC_GLOBAL C<TP>* __restrict__ ne,
+                                          TC_GLOBAL cd* __restrict__ rv, TC_GLOBAL cd* __restrict__ re, size_t gid, bool vrow, const RhsAcc& A, cd pv,
                                           cd pe, double dt, const StepCoef& sc) {
     cd r = {0, 0};
     if (vrow) r = cfma(dt * sc.gamma, A.Nv, K > 0 ? cfma(dt * sc.rho, pv, A.Iv) : A.Iv);
@@ -793,8 +796,8 @@ __device__ __forceinline__ void rhs_store(C<TP>* __restrict__ nv, C<TP>* __restr
 }
 
 template <typename TP, int K>
-__device__ __forceinline__ void rhs_zero_row(C<TP>* __restrict__ nv, C<TP>* __restrict__ ne, cd* __restrict__ rv,
-                                             cd* __restrict__ re, size_t gid) {
+__device__ __forceinline__ void rhs_zero_row(TC_GLOBAL C<TP>* __restrict__ nv, TC_GLOBAL C<TP>* __restrict__ ne,
+                                             TC_GLOBAL cd* __restrict__ rv, TC_GLOBAL cd* __restrict__ re, size_t gid) {
     if (K < 2) {
         nv[gid] = C<TP>{(TP)0, (TP)0};
         ne[gid] = C<TP>{(TP)0, (TP)0};
@@ -822,12 +825,13 @@ __device__ __forceinline__ void pin_both(RhsAcc& A) {
 // further loads nor interleaves points (either would take the register count
 // above two waves per SIMD).
 template <typename TP, int K>
-__device__ __forceinline__ void rhs_lane(const cd* __restrict__ v, const cd* __restrict__ eta,
-                                         const cd* __restrict__ dv, const C<TP>* __restrict__ ps,
-                                         const C<TP>* __restrict__ pnv, const C<TP>* __restrict__ pne,
-                                         C<TP>* __restrict__ nnv, C<TP>* __restrict__ nne, cd* __restrict__ rv,
-                                         cd* __restrict__ re, const double* __restrict__ coef,
-                                         const double* __restrict__ r, int nr, int P, int mode, int n0, int rr,
+__device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, const TC_GLOBAL cd* __restrict__ eta,
+                                         const TC_GLOBAL cd* __restrict__ dv, const TC_GLOBAL C<TP>* __restrict__ ps,
+                                         const TC_GLOBAL C<TP>* __restrict__ pnv,
+                                         const TC_GLOBAL C<TP>* __restrict__ pne, TC_GLOBAL C<TP>* __restrict__ nnv,
+                                         TC_GLOBAL C<TP>* __restrict__ nne, TC_GLOBAL cd* __restrict__ rv,
+                                         TC_GLOBAL cd* __restrict__ re, const TC_CONST double* __restrict__ coef,
+                                         const TC_CONST double* __restrict__ r, int nr, int P, int mode, int n0, int rr,
                                          bool first, bool last, double mm, double al, double nu, double dt,
                                          const StepCoef& sc) {
     const size_t S = (size_t)nr * P;
@@ -909,7 +913,7 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepC
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
     const int rr = g.rhs_rr;
-    const C<TP>* __restrict__ ps = (const C<TP>*)b.ps;
+    const auto* __restrict__ ps = glb((const C<TP>*)b.ps);
     if (blockIdx.y == 1) {  // the mean (0,0) mode: one lane per row
         const int n = blockIdx.x * NT + threadIdx.x;
         if (n < g.nr) rhs_mean_row<TP, K>(g, b, ps, sc, n);
@@ -929,11 +933,11 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepC
     const int j = mode / g.nl;
     const int li = mode - j * g.nl;
     using CT = C<TP>;
-    rhs_lane<TP, K>(b.v, b.eta, b.dv, ps, K > 0 ? (const CT*)b.nv[K > 0 ? K - 1 : 0] : nullptr,
-                    K > 0 ? (const CT*)b.neta[K > 0 ? K - 1 : 0] : nullptr,
-                    K < 2 ? (CT*)b.nv[K < 2 ? K : 0] : nullptr, K < 2 ? (CT*)b.neta[K < 2 ? K : 0] : nullptr,
-                    b.rv, b.re, g.coef, g.r, nr, P, mode, n0, rr, first,
-                    last, g.m[j], g.alpha[li], g.nu, g.dt, sc);
+    rhs_lane<TP, K>(glb(b.v), glb(b.eta), glb(b.dv), ps, glb(K > 0 ? (const CT*)b.nv[K > 0 ? K - 1 : 0] : nullptr),
+                    glb(K > 0 ? (const CT*)b.neta[K > 0 ? K - 1 : 0] : nullptr),
+                    glb(K < 2 ? (CT*)b.nv[K < 2 ? K : 0] : nullptr), glb(K < 2 ? (CT*)b.neta[K < 2 ? K : 0] : nullptr),
+                    glb(b.rv), glb(b.re), cst(g.coef), cst(g.r), nr, P, mode, n0, rr, first, last, glb(g.m)[j],
+                    glb(g.alpha)[li], g.nu, g.dt, sc);
 }
 
 // ---------------------------------------------------------------- k_solve
@@ -1221,12 +1225,13 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
     const bool mirror = (j == 0 && l > 0);
     const int s0 = 1 + seg * L;
     const int len = max(0, min(s0 + L, nr - 1) - s0);
-    const cd* __restrict__ rhs = eqn == 0 ? b.rv : b.re;
-    cd* __restrict__ out = eqn == 0 ? b.v : b.eta;
-    const double* __restrict__ mwall = b.mwall + ((size_t)k * 2 + eqn) * nr;
-    const double* __restrict__ lu = b.lu;
+    const auto* __restrict__ rhs = glb(eqn == 0 ? b.rv : b.re);
+    auto* __restrict__ out = glb(eqn == 0 ? b.v : b.eta);
+    const auto* __restrict__ mwall = glb(b.mwall) + ((size_t)k * 2 + eqn) * nr;
+    const auto* __restrict__ lu = glb(b.lu);
+    const auto* __restrict__ fold = glb(b.fold);
     const size_t fstride = (size_t)nr * g.npairs;  // between the five factor fields
-    const double* __restrict__ lub = lu + lu_index(g, k, eqn, 0, 0, pair);
+    const auto* __restrict__ lub = lu + lu_index(g, k, eqn, 0, 0, pair);
     auto raw = [&](int n) {  // right-hand side of row n before elimination
         cd r = rhs[(size_t)n * P + mode];
         if (mean) r.x -= mwall[n];
@@ -1244,7 +1249,7 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
         cd r[L];
 #pragma unroll
         for (int i = 0; i < L; ++i) r[i] = raw(min(s0 + i, nr - 2));
-        if (s0 == 1) r[0] = cfma(-b.fold[(((size_t)k * 2 + eqn) * 2 + 0) * g.npairs + pair], raw(2), r[0]);
+        if (s0 == 1) r[0] = cfma(-fold[(((size_t)k * 2 + eqn) * 2 + 0) * g.npairs + pair], raw(2), r[0]);
         cd p1 = {0, 0}, p2 = {0, 0};
         double a1 = 1.0, a2 = 0.0, c1 = 0.0, c2 = 1.0;  // responses to y_{s0-1} and y_{s0-2}
 #pragma unroll
@@ -1252,7 +1257,7 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
             if (i < len) {
                 const int n = s0 + i;
                 cd rn = r[i];
-                if (n == nr - 2) rn = cfma(-b.fold[(((size_t)k * 2 + eqn) * 2 + 1) * g.npairs + pair], raw(nr - 3), rn);
+                if (n == nr - 2) rn = cfma(-fold[(((size_t)k * 2 + eqn) * 2 + 1) * g.npairs + pair], raw(nr - 3), rn);
                 const double l2 = lub[(size_t)n * g.npairs], l1 = lub[fstride + (size_t)n * g.npairs];
                 const cd yn = cfma(-l2, p2, cfma(-l1, p1, rn));
                 const double an = -l1 * a1 - l2 * a2, cn = -l1 * c1 - l2 * c2;
@@ -1330,7 +1335,7 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
         d1 = n1;
         d2 = n2;
     }
-    double* mo = eqn == 0 ? b.umean : b.wmean;
+    auto* mo = glb(eqn == 0 ? b.umean : b.wmean);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         if (i < len) {
@@ -1662,7 +1667,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     const int ncols = min(JB, nj - j0);
     const int j = j0 + c;
     const bool active = c < ncols;
-    const double R = glb(g.r)[r];
+    const double R = cst(g.r)[r];
     const size_t Pm = g.P;
     const auto* tw = glb(tw_z<T>(g));
     // a column's transform lives in TL lanes of one wavefront, so its LDS
