@@ -1518,6 +1518,24 @@ constexpr int zlane_pitch(int N) {
     return N + ((16 % jb) == 0 ? 16 / jb : 1);
 }
 
+// The value v of lane src of this wavefront (ds_bpermute: the LDS crossbar,
+// no LDS memory).  Every lane of the wavefront must be active.
+__device__ __forceinline__ int lane_read_b32(int v, int src) { return __builtin_amdgcn_ds_bpermute(src * 4, v); }
+__device__ __forceinline__ C<double> lane_read(C<double> v, int src) {
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, v.x);
+    const unsigned long long y = __builtin_bit_cast(unsigned long long, v.y);
+    const unsigned long long xl = (unsigned)lane_read_b32((int)(unsigned)x, src);
+    const unsigned long long xh = (unsigned)lane_read_b32((int)(unsigned)(x >> 32), src);
+    const unsigned long long yl = (unsigned)lane_read_b32((int)(unsigned)y, src);
+    const unsigned long long yh = (unsigned)lane_read_b32((int)(unsigned)(y >> 32), src);
+    return C<double>{__builtin_bit_cast(double, xl | (xh << 32)), __builtin_bit_cast(double, yl | (yh << 32))};
+}
+__device__ __forceinline__ C<float> lane_read(C<float> v, int src) {
+    const int x = lane_read_b32(__builtin_bit_cast(int, v.x), src);
+    const int y = lane_read_b32(__builtin_bit_cast(int, v.y), src);
+    return C<float>{__builtin_bit_cast(float, x), __builtin_bit_cast(float, y)};
+}
+
 // Wavefront-scope ordering of LDS accesses: a wavefront's LDS instructions
 // execute in order, so a fence that keeps the compiler from moving them
 // across this point is all that lanes of one wavefront need to exchange data.
@@ -1560,8 +1578,8 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
     __shared__ C<T> lds[theta_waves<T>() * W * N];
     __shared__ C<T> twl[lane::tw_size<N>() + 1];  // per-pass twiddles
     if ((int)blockIdx.y >= g.nr || (int)blockIdx.x * theta_waves<T>() * W >= g.nz / 2) return;  // whole block
-    const int wv = threadIdx.x / 64;
-    const int lw = threadIdx.x - wv * 64;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int lw = threadIdx.x & 63;
     const int grp = lw / TL;
     const int gl = lw - grp * TL;
     const int rp = (blockIdx.x * theta_waves<T>() + wv) * W + grp;
@@ -1603,27 +1621,36 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
     C<T>* mine = lds + (wv * W + grp) * N;
     const WaveSync sync;
     // forward-transform product x (slot order of the inverse transforms) and
-    // write its two z rows
+    // write its two z rows.  The transform's outputs stay in registers: lane
+    // gl holds positions gl + TL m, and the mirrored position N - j of its
+    // output j = gl + TL q sits in lane TL - gl at m = P - 1 - q (lane 0
+    // holds its own, at m = P - q), read across lanes.
+    constexpr int QN = (NJ + TL - 1) / TL;
+    static_assert(QN <= P, "kept outputs per lane");
+    const int partner = grp * TL + ((TL - gl) & (TL - 1));
     auto product_out = [&](int prod, const C<T>* a, const C<T>* c) {
         C<T> x[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) x[k] = pmul(a[m_to_last_slot<N>(k)], c[m_to_last_slot<N>(k)]);
-        lane::fft<T, N, -1, false>(mine, x, gl, twl, sync);
-        sync();
+        lane::fft<T, N, -1, true>(mine, x, gl, twl, sync);
+        C<T> hm[QN];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const C<T> got = lane_read(x[m_to_last_slot<N>(P - 1 - q)], partner);
+            hm[q] = gl == 0 ? x[m_to_last_slot<N>((P - q) % P)] : got;
+        }
         if (active) {
             auto* out = pb + (((size_t)prod * nr + r) * nz + z0) * NJ;
 #pragma unroll
-            for (int q = 0; q < (NJ + TL - 1) / TL; ++q) {
+            for (int q = 0; q < QN; ++q) {
                 const int j = gl + q * TL;
                 if ((q + 1) * TL <= NJ || j < NJ) {
-                    const C<T> h = mine[lane::swz<T, N>(j)];
-                    const C<T> hm = mine[lane::swz<T, N>(j == 0 ? 0 : N - j)];
-                    out[j] = C<T>{(T)0.5 * (h.x + hm.x), (T)0.5 * (h.y - hm.y)};
-                    out[NJ + j] = C<T>{(T)0.5 * (h.y + hm.y), (T)0.5 * (hm.x - h.x)};
+                    const C<T> h = x[m_to_last_slot<N>(q)];
+                    out[j] = C<T>{(T)0.5 * (h.x + hm[q].x), (T)0.5 * (h.y - hm[q].y)};
+                    out[NJ + j] = C<T>{(T)0.5 * (h.y + hm[q].y), (T)0.5 * (hm[q].x - h.x)};
                 }
             }
         }
-        sync();
     };
     // u and v first, w after the three products that need only u and v, so
     // that at most three transform-sized register sets are live at a time
