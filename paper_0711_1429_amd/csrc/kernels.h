@@ -29,6 +29,32 @@ __device__ __forceinline__ TC_GLOBAL T* glb(T* p) {
     return (TC_GLOBAL T*)p;
 }
 
+// base[i] with a 32-bit element offset (the byte offset must stay below
+// 4 GiB): with a wave-uniform base the access compiles to a scalar base plus
+// a 32-bit lane offset instead of a 64-bit address per lane.
+template <typename T>
+__device__ __forceinline__ TC_GLOBAL T& at(TC_GLOBAL T* base, unsigned i) {
+    return *(TC_GLOBAL T*)((TC_GLOBAL char*)base + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const TC_GLOBAL T& at(const TC_GLOBAL T* base, unsigned i) {
+    return *(const TC_GLOBAL T*)((const TC_GLOBAL char*)base + i * (unsigned)sizeof(T));
+}
+
+// p, the same in every lane, held in scalar registers (so that the compiler
+// keeps it as the scalar base of the accesses through it)
+template <typename T>
+__device__ __forceinline__ T* uniform(T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return (T*)(((unsigned long long)hi << 32) | lo);
+#else
+    return p;
+#endif
+}
+
 // A table that no kernel writes, in the constant address space: reads of it
 // at wave-uniform addresses compile to scalar loads.
 #if defined(__HIP_DEVICE_COMPILE__)

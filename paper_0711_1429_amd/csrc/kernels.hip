@@ -1595,6 +1595,7 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
     constexpr int KT = (N - 1) / 3, NJ = KT + 1;
     auto load = [&](int fl, C<T>* x) {
         const auto* row0 = zb + (((size_t)fl * nr + r) * nz + z0) * NJ;
+        if constexpr (W == 1) row0 = uniform(row0);  // one row pair per wavefront
         const auto* row1 = row0 + NJ;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -1604,14 +1605,14 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
             C<T> h = {(T)0, (T)0};
             if (active) {
                 if (low_all || (!low_none && p <= KT)) {
-                    C<T> a = row0[p], c = row1[p];
+                    C<T> a = at(row0, (unsigned)p), c = at(row1, (unsigned)p);
                     if (k == 0 && p == 0) {
                         a.y = (T)0;
                         c.y = (T)0;
                     }
                     h = C<T>{a.x - c.y, a.y + c.x};
                 } else if (high_all || (!high_none && p >= N - KT)) {
-                    const C<T> a = row0[N - p], c = row1[N - p];
+                    const C<T> a = at(row0, (unsigned)(N - p)), c = at(row1, (unsigned)(N - p));
                     h = C<T>{a.x + c.y, c.x - a.y};
                 }
             }
@@ -1641,13 +1642,14 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
         }
         if (active) {
             auto* out = pb + (((size_t)prod * nr + r) * nz + z0) * NJ;
+            if constexpr (W == 1) out = uniform(out);  // one row pair per wavefront
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
                 const int j = gl + q * TL;
                 if ((q + 1) * TL <= NJ || j < NJ) {
                     const C<T> h = x[m_to_last_slot<N>(q)];
-                    out[j] = C<T>{(T)0.5 * (h.x + hm[q].x), (T)0.5 * (h.y - hm[q].y)};
-                    out[NJ + j] = C<T>{(T)0.5 * (h.y + hm[q].y), (T)0.5 * (hm[q].x - h.x)};
+                    at(out, (unsigned)j) = C<T>{(T)0.5 * (h.x + hm[q].x), (T)0.5 * (h.y - hm[q].y)};
+                    at(out, (unsigned)(NJ + j)) = C<T>{(T)0.5 * (h.y + hm[q].y), (T)0.5 * (hm[q].x - h.x)};
                 }
             }
         }
@@ -1690,7 +1692,11 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     const int r = blockIdx.y;
     const int j0 = blockIdx.x * JB;
     if (r >= g.nr || j0 >= g.nj) return;  // past this instance's extents (whole block)
-    const int nj = g.nj, nl = g.nl, kz = g.kz;
+    const int nj = g.nj;
+    // K_z = (N - 1) / 3 is fixed by N: which of the kept band, the zero band
+    // and the mirrored band a register slot covers is known at compile time
+    // for every slot but one or two
+    constexpr int KZ = (N - 1) / 3, NL = 2 * KZ + 1;
     const int ncols = min(JB, nj - j0);
     const int j = j0 + c;
     const bool active = c < ncols;
@@ -1705,22 +1711,29 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
     C<T> X[3][P];
     const double mm = active ? glb(g.m)[j] : 0.0;
+    const auto* vr = v + (size_t)r * Pm;  // plane r
+    const auto* er = eta + (size_t)r * Pm;
+    const auto* dr = dv + (size_t)r * Pm;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         const int q = gl + k * TL;
-        const int l = q <= kz ? q : q - N;
+        const bool low_all = k * TL + TL - 1 <= KZ, low_none = k * TL > KZ;
+        const bool high_all = k * TL >= N - KZ, high_none = k * TL + TL - 1 < N - KZ;
+        const bool low = low_all || (!low_none && q <= KZ);
+        const bool high = !low && (high_all || (!high_none && q >= N - KZ));
+        const int l = low ? q : q - N;
         C<T> xu = {(T)0, (T)0}, xv = xu, xw = xu;
-        if (active && l >= -kz) {
-            const size_t e = (size_t)r * Pm + (size_t)j * nl + (l + kz);
+        if (active && (low || high)) {
+            const unsigned e = (unsigned)(j * NL + (l + KZ));
             if (j == 0 && l == 0) {
                 xu.x = (T)umean[r];
                 xw.x = (T)wmean[r];
             } else {
-                const double al = glb(g.alpha)[l + kz];
+                const double al = glb(g.alpha)[l + KZ];
                 const double a = R * R / (al * al * R * R + mm * mm);
-                const cd vv = v[e];
+                const cd vv = at(vr, e);
                 cd u, w;
-                recover(vv, eta[e], dv[e], R, mm, al, a, u, w);
+                recover(vv, at(er, e), at(dr, e), R, mm, al, a, u, w);
                 xu = C<T>{(T)u.x, (T)u.y};
                 xv = C<T>{(T)vv.x, (T)vv.y};
                 xw = C<T>{(T)w.x, (T)w.y};
@@ -1730,6 +1743,22 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
         X[1][k] = xv;
         X[2][k] = xw;
     }
+    // transposed write-out: tile element e of this lane is idx = threadIdx.x +
+    // e NTH, row z = idx / ncols and column cc = idx mod ncols, at these
+    // offsets in the plane and in LDS (-1: past the tile)
+    int goff[P], loff[P];
+    {
+        const bool full = ncols == JB;  // every block but an instance's last
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            const int idx = threadIdx.x + e * NTH;
+            const int z = full ? idx / JB : idx / ncols;
+            const int cc = idx - z * (full ? JB : ncols);
+            const bool ok = idx < ncols * N;
+            goff[e] = ok ? z * nj + j0 + cc : -1;
+            loff[e] = ok ? cc * PITCH + z : -1;
+        }
+    }
     __syncthreads();  // twiddles in place
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -1737,12 +1766,10 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
 #pragma unroll
         for (int q = 0; q < P; ++q) lds[c * PITCH + gl + TL * lane::last_slot_to_m<N>(q)] = X[f][q];
         __syncthreads();
-        auto* out = zb + ((size_t)f * g.nr + r) * N * nj;
-        for (int idx = threadIdx.x; idx < ncols * N; idx += NTH) {
-            const int z = idx / ncols;
-            const int cc = idx - z * ncols;
-            out[(size_t)z * nj + j0 + cc] = lds[cc * PITCH + z];
-        }
+        auto* out = uniform(zb + ((size_t)f * g.nr + r) * N * nj);
+#pragma unroll
+        for (int e = 0; e < P; ++e)
+            if (goff[e] >= 0) at(out, (unsigned)goff[e]) = lds[loff[e]];
         __syncthreads();
     }
 }
@@ -1763,7 +1790,8 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
     const int r = blockIdx.y;
     const int j0 = blockIdx.x * JB;
     if (r >= g.nr || j0 >= g.nj) return;  // past this instance's extents (whole block)
-    const int nj = g.nj, nl = g.nl, kz = g.kz;
+    const int nj = g.nj;
+    constexpr int KZ = (N - 1) / 3, NL = 2 * KZ + 1;  // K_z is fixed by N
     const int ncols = min(JB, nj - j0);
     const bool active = c < ncols;
     const size_t Pm = g.P;
@@ -1774,33 +1802,41 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
     const WaveSync sync;
     __shared__ C<T> twl[lane::tw_size<N>() + 1];
     lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
+    // tile element e of this lane is idx = threadIdx.x + e NTH, row z =
+    // idx / ncols and column cc = idx mod ncols, the same for every product:
+    // its offset in the plane and in LDS are formed once (-1: past the tile)
+    int goff[P], loff[P];
+    {
+        const bool full = ncols == JB;  // every block but an instance's last
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            const int idx = threadIdx.x + e * NTH;
+            const int z = full ? idx / JB : idx / ncols;
+            const int cc = idx - z * (full ? JB : ncols);
+            const bool ok = idx < ncols * N;
+            goff[e] = ok ? z * nj + j0 + cc : -1;
+            loff[e] = ok ? cc * PITCH + z : -1;
+        }
+    }
     // the next product's tile (P values per lane) is fetched into registers
     // while the current one is transformed
     C<T> nxt[P];
     auto fetch = [&](int f) {
-        const auto* in = pb + ((size_t)f * g.nr + r) * N * nj;
+        const auto* in = uniform(pb + ((size_t)f * g.nr + r) * N * nj);
 #pragma unroll
         for (int e = 0; e < P; ++e) {
-            const int idx = threadIdx.x + e * NTH;
-            const int z = idx / ncols;
-            const int cc = idx - z * ncols;
             // past the tile the load repeats the plane's first element (in
             // bounds) and its value is dropped
-            const bool ok = idx < ncols * N;
-            const C<T> t = in[ok ? (size_t)z * nj + j0 + cc : 0];
-            nxt[e] = ok ? t : C<T>{(T)0, (T)0};
+            const C<T> t = at(in, (unsigned)max(goff[e], 0));
+            nxt[e] = goff[e] >= 0 ? t : C<T>{(T)0, (T)0};
         }
     };
     fetch(0);
 #pragma unroll 1
     for (int f = 0; f < 6; ++f) {
 #pragma unroll
-        for (int e = 0; e < P; ++e) {
-            const int idx = threadIdx.x + e * NTH;
-            const int z = idx / ncols;
-            const int cc = idx - z * ncols;
-            if (idx < ncols * N) lds[cc * PITCH + z] = nxt[e];
-        }
+        for (int e = 0; e < P; ++e)
+            if (loff[e] >= 0) lds[loff[e]] = nxt[e];
         __syncthreads();  // also completes the twiddle table on the first pass
         if (f < 5) fetch(f + 1);
         C<T> x[P];
@@ -1809,12 +1845,12 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
         sync();
         lane::fft<T, N, -1, true>(lds + c * PITCH, x, gl, twl, sync);
         if (active) {
-            auto* out = ps + (size_t)f * g.nr * Pm + (size_t)r * Pm + (size_t)(j0 + c) * nl;
+            auto* out = uniform(ps + (size_t)f * g.nr * Pm + (size_t)r * Pm);  // plane r of product f
 #pragma unroll
             for (int s = 0; s < P; ++s) {
                 const int q = gl + TL * lane::last_slot_to_m<N>(s);
-                const int l = q <= kz ? q : q - N;
-                if (l >= -kz) out[l + kz] = cscale(x[s], scale);
+                const int l = q <= KZ ? q : q - N;
+                if (l >= -KZ) at(out, (unsigned)((j0 + c) * NL + l + KZ)) = cscale(x[s], scale);
             }
         }
         __syncthreads();  // every column read before the next transposed load
@@ -1895,6 +1931,8 @@ void theta_lane(const Batch& B, hipStream_t s) {
 
 template <typename T>
 bool zinv_fast(const Batch& B, hipStream_t s) {
+    // the lane kernels take K_z = (nz - 1) / 3 as a compile-time constant
+    if (B.g.kz != (B.g.nz - 1) / 3 || B.g.nl != 2 * B.g.kz + 1) return false;
     switch (B.g.nz) {
 #define TC_CASE(N) case N: zinv_lane<T, N>(B, s); return true;
         TC_LANE_SIZES(TC_CASE)
@@ -1904,6 +1942,7 @@ bool zinv_fast(const Batch& B, hipStream_t s) {
 }
 template <typename T>
 bool zfwd_fast(const Batch& B, hipStream_t s) {
+    if (B.g.kz != (B.g.nz - 1) / 3 || B.g.nl != 2 * B.g.kz + 1) return false;
     switch (B.g.nz) {
 #define TC_CASE(N) case N: zfwd_lane<T, N>(B, s); return true;
         TC_LANE_SIZES(TC_CASE)
