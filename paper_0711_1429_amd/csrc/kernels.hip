@@ -594,12 +594,6 @@ __global__ __launch_bounds__(NT) void k_zfwd(const InstDev* __restrict__ I, int 
 }
 
 // ---------------------------------------------------------------- k_rhs
-template <typename TP>
-__device__ __forceinline__ cd ldp(const TC_GLOBAL C<TP>* p, size_t i) {
-    const C<TP> x = p[i];
-    return cd{(double)x.x, (double)x.y};
-}
-
 // One lane per (mode, chunk of rr consecutive rows of 2..nr-3, the rows
 // whose 5-point stencils are centred).  The lane walks the chunk's rr + 4
 // stencil points in increasing r, forms the per-point operands of every
@@ -1536,6 +1530,16 @@ __device__ __forceinline__ C<float> lane_read(C<float> v, int src) {
     return C<float>{__builtin_bit_cast(float, x), __builtin_bit_cast(float, y)};
 }
 
+// The block of a plane's column groups that runs block x: with the groups
+// paired so that x and x + 8 (which the dispatcher sends to the same XCD, and
+// so the same L2) take adjacent groups.  A complex-float group of fewer than
+// 16 columns covers part of each 128-byte line of a z row; paired, two such
+// parts are fetched through one L2.  Identity unless gx is a multiple of 16.
+__device__ __forceinline__ int xcd_pair(int x, int gx) {
+    if (gx % 16) return x;
+    return (x & ~15) + 2 * (x & 7) + ((x >> 3) & 1);
+}
+
 // Wavefront-scope ordering of LDS accesses: a wavefront's LDS instructions
 // execute in order, so a fence that keeps the compiler from moving them
 // across this point is all that lanes of one wavefront need to exchange data.
@@ -1690,7 +1694,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     const int c = threadIdx.x / TL;
     const int gl = threadIdx.x - c * TL;
     const int r = blockIdx.y;
-    const int j0 = blockIdx.x * JB;
+    const int j0 = (sizeof(T) == 4 ? xcd_pair(blockIdx.x, gridDim.x) : (int)blockIdx.x) * JB;
     if (r >= g.nr || j0 >= g.nj) return;  // past this instance's extents (whole block)
     const int nj = g.nj;
     // K_z = (N - 1) / 3 is fixed by N: which of the kept band, the zero band
@@ -1788,7 +1792,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane
     const int c = threadIdx.x / TL;
     const int gl = threadIdx.x - c * TL;
     const int r = blockIdx.y;
-    const int j0 = blockIdx.x * JB;
+    const int j0 = (sizeof(T) == 4 ? xcd_pair(blockIdx.x, gridDim.x) : (int)blockIdx.x) * JB;
     if (r >= g.nr || j0 >= g.nj) return;  // past this instance's extents (whole block)
     const int nj = g.nj;
     constexpr int KZ = (N - 1) / 3, NL = 2 * KZ + 1;  // K_z is fixed by N
