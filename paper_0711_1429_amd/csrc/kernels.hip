@@ -1560,9 +1560,10 @@ __host__ __device__ constexpr int m_to_last_slot(int m) {
     return 0;
 }
 
-// wavefronts per block of the theta kernel (measured best: 4 in FP64, 2 in FP32)
+// wavefronts per block of the theta kernel (measured best: 1 in FP64, so that
+// every wavefront starts and ends on its own, 2 in FP32)
 template <typename T>
-constexpr int theta_waves() { return sizeof(T) == 8 ? 4 : 2; }
+constexpr int theta_waves() { return sizeof(T) == 8 ? 1 : 2; }
 
 // theta rows: each wavefront owns W = 64 / TL packed row pairs (z0, z0 + 1)
 // and does everything for them.  It loads u, v and w, inverse-transforms them
