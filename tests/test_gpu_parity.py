@@ -235,6 +235,28 @@ def test_lane_and_generic_paths_agree_at_turbulent_size():
         assert err < 1e-13
 
 
+def test_mixed_products_at_turbulent_size():
+    """FP32 transforms on the full turbulent-case grid, the size at which the
+    FP32 z kernels pair their column groups across XCDs, give the products of
+    the FP64 transforms to single-precision rounding (both lane and generic
+    kernels)."""
+    w = workload("tc-turbulent-fp64")
+    from tests.helpers import abi_geometry, fields_for
+    ref = tcb.Solver(abi_geometry(w))
+    f = fields_for(w, ref.grid())
+    ref.load_fields(*f)
+    pr = ref.products()
+    for flags in (0, tcb.TC_FLAG_GENERIC_FFT):
+        m = tcb.Solver(abi_geometry(w, tcb.TC_PREC_MIXED, flags=flags))
+        m.load_fields(*f)
+        pm = m.products()
+        for k in pr:
+            err = rel_l2(pm[k], pr[k])
+            print("mixed vs fp64", flags, k, f"{err:.2e}", flush=True)
+            assert 1e-10 < err < 2e-6
+        del m
+
+
 def test_graph_replays_match_eager_steps():
     """Whole-step graph replays, with eager work (field reads) and
     synchronisation between them, give bit-identical states to eager launches."""
