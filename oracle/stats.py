@@ -17,6 +17,13 @@ Kinetic energy: E = sum_n w_n r_n sum_{j,l} c_j (|u|^2 + |v|^2 + |w|^2)
 / (2 sum_n w_n r_n) with trapezoidal weights w_n and c_0 = 1, c_{j>0} = 2
 (Parseval over the stored half spectrum).  ``energy`` includes the mean flow,
 ``energy_pert`` excludes the (0,0) mode.
+
+Radial profiles (Sec. 5: mean azimuthal velocity and the variances of the
+velocity fluctuations across the gap): at each radial node, averages over
+theta and z.  The mean profiles are the (0,0) mode; the fluctuation of f is
+f minus its plane mean, so its variance is, by Parseval over the stored half
+spectrum, <f'f'>(r) = sum_{(j,l) != (0,0)} c_j |f_hat(r, j, l)|^2, and the
+covariance <v'w'>(r) = sum c_j Re(v_hat conj(w_hat)).
 """
 
 import numpy as np
@@ -71,4 +78,23 @@ def statistics(orc, u, w):
         "energy_pert": float(np.dot(wr, per_r_pert) / (2 * vol)),
         "steps": orc.steps,
         "nonfinite": int(not finite),
+    }
+
+
+def plane_profiles(orc, u, w):
+    """Mean profiles and fluctuation (co)variances at every radial node, from
+    the spectral velocities u, w (mean in the (0,0) slot) and orc.v.  Returns
+    a dict of arrays of length N_r: u_mean, w_mean, uu, vv, ww, vw."""
+    d = orc.disc
+    cj = np.where(np.arange(d.nj) == 0, 1.0, 2.0)
+    c = np.repeat(cj, d.nl)[None, :].copy()
+    c[0, orc.mean_index] = 0.0  # fluctuations: the plane mean is left out
+    v = orc.v
+    return {
+        "u_mean": orc.u_mean.copy(),
+        "w_mean": orc.w_mean.copy(),
+        "uu": (c * np.abs(u) ** 2).sum(axis=1),
+        "vv": (c * np.abs(v) ** 2).sum(axis=1),
+        "ww": (c * np.abs(w) ** 2).sum(axis=1),
+        "vw": (c * (v * np.conj(w)).real).sum(axis=1),
     }

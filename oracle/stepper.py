@@ -258,3 +258,7 @@ class Oracle:
     def stats(self):
         dv, u, w, c = self.velocity()
         return st.statistics(self, u, w)
+
+    def profiles(self):
+        dv, u, w, c = self.velocity()
+        return st.plane_profiles(self, u, w)
