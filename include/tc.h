@@ -180,6 +180,15 @@ int tc_velocity(tc_ctx* ctx, int inst, double* u_hat, double* w_hat);
  * complex128 in that order. */
 int tc_products(tc_ctx* ctx, int inst, double* prod);
 
+/* Radial profiles of the statistics Sec. 5 reports across the gap: at each
+ * radial node r_n, averages over theta and z of the current state, written
+ * to out[6][nr] (host memory, caller-owned): the mean axial and azimuthal
+ * velocities u_mean, w_mean, the variances <u'u'>, <v'v'>, <w'w'> of the
+ * fluctuations about the plane mean and the covariance <v'w'>, in units of
+ * W_i (squared).  Computed in FP64 by Parseval over the stored half
+ * spectrum; synchronous.  Time averages are the caller's (sum calls). */
+int tc_profiles(tc_ctx* ctx, int inst, double* out);
+
 /* Statistics of instance `inst` (FP64 device reductions, fixed order). */
 int tc_stats(tc_ctx* ctx, int inst, tc_stats_t* out);
 

@@ -189,6 +189,8 @@ void launch_solve(const Batch& B, int k, hipStream_t s);
 void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>* w, hipStream_t s);
 // energy reductions + finite check + statistics into b.stats
 void launch_stats(const DevGeom& g, const DevBuf& b, hipStream_t s);
+// radial profiles [6][nr] (mean u, mean w, <u'u'>, <v'v'>, <w'w'>, <v'w'>) into device memory out
+void launch_profiles(const DevGeom& g, const DevBuf& b, double* out, hipStream_t s);
 // finite check of the state into b.flags[0]
 void launch_finite(const Batch& B, hipStream_t s);
 

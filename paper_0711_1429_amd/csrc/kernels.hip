@@ -1415,6 +1415,50 @@ __global__ __launch_bounds__(RED_NT) void k_energy(DevGeom g, DevBuf b) {
     }
 }
 
+// Radial profiles (Sec. 5): at node n, the mean profiles and the plane
+// averages of the fluctuations' products, by Parseval over the stored half
+// spectrum without the (0,0) mode (c_0 = 1, c_{j>0} = 2): <u'u'>, <v'v'>,
+// <w'w'> and <v'w'>.  One block per node, sums in a fixed order; out is
+// [6][nr]: u_mean, w_mean, uu, vv, ww, vw.
+__global__ __launch_bounds__(RED_NT) void k_profiles(DevGeom g, DevBuf b, double* __restrict__ out) {
+    __shared__ double sa[4][RED_NT];
+    const int n = blockIdx.x;
+    const size_t P = g.P;
+    const double R = g.r[n];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int mode = threadIdx.x; mode < g.P; mode += RED_NT) {
+        if (mode == g.mean) continue;
+        const int j = mode / g.nl;
+        const int li = mode - j * g.nl;
+        const size_t gid = (size_t)n * P + mode;
+        const double cj = j == 0 ? 1.0 : 2.0;
+        const double mm = g.m[j], al = g.alpha[li];
+        const double a = R * R / (al * al * R * R + mm * mm);
+        const cd v = b.v[gid];
+        cd u, w;
+        recover(v, b.eta[gid], b.dv[gid], R, mm, al, a, u, w);
+        acc[0] += cj * (u.x * u.x + u.y * u.y);
+        acc[1] += cj * (v.x * v.x + v.y * v.y);
+        acc[2] += cj * (w.x * w.x + w.y * w.y);
+        acc[3] += cj * (v.x * w.x + v.y * w.y);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sa[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int h = RED_NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sa[k][threadIdx.x] += sa[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[n] = b.umean[n];
+        out[g.nr + n] = b.wmean[n];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[(size_t)(2 + k) * g.nr + n] = sa[k][0];
+    }
+}
+
 // Sums the partials in a fixed order and evaluates the wall shear
 // g = |D w - w / r| at both walls from the one-sided compact rows.
 __global__ __launch_bounds__(RED_NT) void k_stats_final(DevGeom g, DevBuf b, int nblocks) {
@@ -2090,6 +2134,10 @@ void launch_solve(const Batch& B, int k, hipStream_t s) {
 void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>* w, hipStream_t s) {
     const size_t total = (size_t)g.nr * g.P;
     hipLaunchKernelGGL(k_velocity, dim3((unsigned)((total + NT - 1) / NT)), dim3(NT), 0, s, g, b, u, w);
+}
+
+void launch_profiles(const DevGeom& g, const DevBuf& b, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_profiles, dim3(g.nr), dim3(RED_NT), 0, s, g, b, out);
 }
 
 void launch_stats(const DevGeom& g, const DevBuf& b, hipStream_t s) {

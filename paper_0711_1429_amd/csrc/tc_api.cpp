@@ -759,6 +759,20 @@ int tc_products(tc_ctx* c, int inst, double* prod) {
     return TC_OK;
 }
 
+int tc_profiles(tc_ctx* c, int inst, double* out) {
+    Instance* in = get_inst(c, inst);
+    if (!in || !out) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    launch_dv(batch_of(*in), c->stream);
+    // rv is scratch between substeps; 6 nr doubles fit in its 2 nr P
+    double* dev = reinterpret_cast<double*>(in->b.rv);
+    launch_profiles(in->g, in->b, dev, c->stream);
+    if (int rc = check_launch(c, "profiles")) return rc;
+    HIPCHK(c, hipMemcpyAsync(out, dev, (size_t)6 * in->s.nr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TC_OK;
+}
+
 int tc_stats(tc_ctx* c, int inst, tc_stats_t* out) {
     Instance* in = get_inst(c, inst);
     if (!in || !out) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;

@@ -75,6 +75,7 @@ _SIGNATURES = {
     "tc_substep": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_velocity": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
     "tc_products": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "tc_profiles": (ctypes.c_int, [_P, ctypes.c_int, _D]),
     "tc_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TcStats)]),
     "tc_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -215,6 +216,12 @@ class Solver:
         p = np.empty((6,) + shape, dtype=np.complex128)
         self._check(self.lib.tc_products(self.ctx, inst, p.ctypes.data_as(_D)))
         return dict(zip(("uu", "uv", "uw", "vv", "vw", "ww"), p))
+
+    def profiles(self, inst=0):
+        nr = self.mode_shape(inst)[0]
+        out = np.empty((6, nr), dtype=np.float64)
+        self._check(self.lib.tc_profiles(self.ctx, inst, out.ctypes.data_as(_D)))
+        return dict(zip(("u_mean", "w_mean", "uu", "vv", "ww", "vw"), out))
 
     def stats(self, inst=0):
         s = TcStats()

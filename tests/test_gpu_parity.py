@@ -98,6 +98,34 @@ def test_medium_grid_three_steps(flags):
     _compare_state(orc, gpu, label="medium step 3")
 
 
+@pytest.mark.parametrize("name,steps,prec", [("tc-small-fp64", 5, tcb.TC_PREC_FP64),
+                                              ("tc-medium-fp64", 2, tcb.TC_PREC_FP64),
+                                              ("tc-medium-fp64", 2, tcb.TC_PREC_MIXED)])
+def test_radial_profiles(name, steps, prec):
+    """Mean profiles and fluctuation (co)variances per radial node (Sec. 5
+    statistics) against the oracle's Parseval sums: on the seeded initial
+    state, then after both sides stepped on their own (to FP64 rounding; the
+    mixed path to its FP32 transform error)."""
+    w = workload(name)
+    orc, gpu = pair(w, precision=prec)
+    tol = TOL if prec == tcb.TC_PREC_FP64 else 1e-5
+    for stage in ("initial", "stepped"):
+        if stage == "stepped":
+            orc.step(steps)
+            gpu.step(steps)
+        ref = orc.profiles()
+        got = gpu.profiles()
+        for k in ref:
+            scale = np.abs(ref[k]).max()
+            if scale == 0:  # e.g. no axial mean flow in the initial state
+                assert np.all(got[k] == 0), k
+                continue
+            err = np.abs(got[k] - ref[k]).max() / scale
+            print("profile", name, prec, stage, k, f"{err:.2e}", flush=True)
+            assert err < (TOL if stage == "initial" else tol)
+        assert np.all(got["vv"] >= 0) and got["vv"][0] == 0 and got["vv"][-1] == 0
+
+
 @PATHS
 @pytest.mark.parametrize("sizes", [dict(nr=7, ntheta=4, nz=4), dict(nr=9, ntheta=48, nz=36, stretch=1.0),
                                    dict(nr=20, ntheta=12, nz=96), dict(nr=11, ntheta=96, nz=6),

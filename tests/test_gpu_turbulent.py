@@ -12,6 +12,12 @@ equal to the radius ratio within 0.18 %, and an angular momentum r <w> of
 nearly 0.5 R_i W_i across the core.  The bounds below allow for the finite
 averaging time (the paper quotes about 1 %) and a radial grid that the paper
 does not specify.
+
+Sec. 5 also describes the variances of the velocity fluctuations across the
+gap (a figure, no table): the streamwise (azimuthal, w) component has the
+highest levels and is more intense over the outer wall, and the wall-normal
+(radial, v) component peaks in the middle of the gap.  Those shape features
+are checked on the time-averaged profiles.
 """
 
 import os
@@ -41,12 +47,15 @@ def test_turbulent_case_friction_reynolds_numbers():
     t_skip = min(150.0, 0.3 * t_end)  # d / W_i
     chunk = 250
     samples = []
+    prof = None
     t0 = time.time()
     while True:
         g.step(chunk)
         s = g.stats()
         if s["time"] > t_skip:
             samples.append((s["tau_in"], s["tau_out"]))
+            p = g.profiles()
+            prof = p if prof is None else {k: prof[k] + p[k] for k in prof}
         if int(round(s["time"] / dt)) % (20 * chunk) == 0:
             print(f"t = {s['time']:7.1f} d/W_i  Re_tau in {s['retau_in']:6.1f} out {s['retau_out']:6.1f}  "
                   f"({time.time() - t0:.0f} s)", flush=True)
@@ -65,3 +74,14 @@ def test_turbulent_case_friction_reynolds_numbers():
     assert abs(retau[1] / 167.7 - 1) < 0.02
     assert abs(retau[1] / retau[0] / zeta - 1) < 0.015
     assert np.all(np.abs(core - 0.5) < 0.05)
+    # time-averaged fluctuation variances (the mean of the per-sample plane averages)
+    prof = {k: a / len(samples) for k, a in prof.items()}
+    y = (r - r[0]) / (r[-1] - r[0])  # 0 at the inner wall, 1 at the outer
+    inner, outer = y < 0.5, y >= 0.5
+    for k in ("uu", "vv", "ww"):
+        i = int(np.argmax(prof[k]))
+        print(f"<{k[0]}'{k[0]}'>: peak {prof[k][i]:.4e} at y = {y[i]:.3f}; inner-half peak "
+              f"{prof[k][inner].max():.4e}, outer-half peak {prof[k][outer].max():.4e}", flush=True)
+    assert prof["ww"].max() > prof["uu"].max() and prof["ww"].max() > prof["vv"].max()
+    assert prof["ww"][outer].max() > prof["ww"][inner].max()
+    assert 0.25 < y[int(np.argmax(prof["vv"]))] < 0.75
