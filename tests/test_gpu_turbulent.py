@@ -1,5 +1,5 @@
 """The paper's turbulent case (Sec. 4, Sec. 5) on the GPU path: a long run,
-skipped unless TC_LONG_RUNS is set (about 10 minutes of an MI355X in FP64).
+skipped unless TC_LONG_RUNS is set (about 8 minutes of an MI355X in FP64).
 
 Radius ratio 0.882, Re = 10500 (full gap), the default box (L_theta = 10 pi h
 at mid-gap, L_z = 5h), 129 radial points (tanh stretching 1.5), 768 x 384
@@ -35,7 +35,7 @@ HALF_GAP_TIMES = float(os.environ.get("TC_TURBULENT_T", "1000"))  # run length i
 
 @pytest.mark.gpu
 @pytest.mark.slow
-@pytest.mark.skipif(not LONG, reason="long run (about 10 minutes): set TC_LONG_RUNS=1")
+@pytest.mark.skipif(not LONG, reason="long run (about 8 minutes): set TC_LONG_RUNS=1")
 def test_turbulent_case_friction_reynolds_numbers():
     zeta, re = 0.882, 10500.0
     dt = 0.006  # 0.012 h / W_i in units of d / W_i
