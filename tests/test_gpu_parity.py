@@ -140,6 +140,37 @@ def test_ragged_and_degenerate_sizes(sizes, flags):
     _compare_state(orc, gpu, tol=TOL, label=str(sizes))
 
 
+@pytest.mark.parametrize("sizes", [dict(nr=9, ntheta=729, nz=192), dict(nr=9, ntheta=96, nz=384)])
+def test_mixed_precision_paired_column_groups(sizes):
+    """Mixed precision where the FP32 z kernels pair their column groups
+    across XCDs (16 or more groups per plane): N_theta = 729 gives 243
+    columns, so the last group of 16 is partial (3 columns); N_z = 384 with
+    N_theta = 96 gives 4 groups (no pairing).  The products of the FP32
+    transforms match the FP64 ones to single-precision rounding (a column
+    handled by the wrong block would be off by O(1)), and two steps track the
+    oracle to the FP32 transform error (eta, the smallest field, carries the
+    largest relative error)."""
+    from tests.helpers import abi_geometry, fields_for
+    w = workload("tc-small-fp64", amplitude=1e-2, **sizes)
+    ref = tcb.Solver(abi_geometry(w))
+    mix = tcb.Solver(abi_geometry(w, tcb.TC_PREC_MIXED))
+    f = fields_for(w, ref.grid())
+    ref.load_fields(*f)
+    mix.load_fields(*f)
+    pr, pm = ref.products(), mix.products()
+    for k in pr:
+        err = rel_l2(pm[k], pr[k])
+        print("mixed products", sizes, k, f"{err:.2e}", flush=True)
+        assert 1e-10 < err < 2e-6
+    del ref, mix
+    orc, gpu = pair(w, precision=tcb.TC_PREC_MIXED)
+    for s in range(2):
+        orc.step(1)
+        gpu.step(1)
+    errs = _compare_state(orc, gpu, tol=1e-4, label="mixed " + str(sizes))
+    assert max(errs.values()) > 1e-12  # the FP32 stages really ran
+
+
 def test_rotating_outer_wall_and_custom_domain():
     w = workload("tc-small-fp64", zeta=0.5, re=120.0, re_outer=-30.0, lz=2.0, theta_period=np.pi,
                  amplitude=1e-2)
