@@ -200,14 +200,24 @@ int tc_stats(tc_ctx* ctx, int inst, tc_stats_t* out);
 int tc_use_graphs(tc_ctx* ctx, int enable);
 
 /* Pick, by timing on the device, the launch parameters that do not change the
- * method: the rows per chunk of the explicit-term kernel (21, 16, 11 or 6) and
- * the segment shape of the radial solve (8 x 4, 8 x 8 or 16 x 8 rows), per
- * launch group.  Runs one substep to fill the intermediates, times `repeats`
+ * method: the rows per chunk of the explicit-term kernel (the columns split
+ * into 1, 2, 3, 4, 5, 6, 8 or 10 chunks, each instance's rows divided evenly,
+ * or 21, 16, 11 or 6 rows for every instance) and the segment shape of the
+ * radial solve (8 x 4, 8 x 8 or 16 x 8 rows), per launch group.  Runs one substep to fill the intermediates, times `repeats`
  * launches (1..1000) of each candidate and restores the state, the N
  * registers and the time exactly, so the fields are unchanged on return.
  * Allocates a temporary copy of the state (freed before returning).  The
  * step graph is recaptured on the next tc_step. */
 int tc_autotune(tc_ctx* ctx, int repeats);
+
+/* Set the rows per chunk of the explicit-term kernel for instance `inst`
+ * (1 <= rows <= nr - 4, else TC_EINVAL and nothing changes): each radial
+ * column is walked in ceil((nr - 4) / rows) chunks.  Every row's terms are
+ * summed in the same order whatever the chunking, so the results are
+ * bit-identical for every value; only the speed changes.  Lets a caller
+ * reuse a tuning found earlier.  The step graph is recaptured on the next
+ * tc_step. */
+int tc_set_rhs_rows(tc_ctx* ctx, int inst, int rows);
 
 /* The launch parameters in use for instance `inst` (after tc_create, or
  * after tc_autotune): rows per chunk of the explicit-term kernel, and the

@@ -177,7 +177,7 @@ enum Stage { ST_DV, ST_ZINV, ST_THETA, ST_ZFWD, ST_RHS, ST_SOLVE, ST_COUNT };
 long long stage_key(int stage, const DevGeom& g);
 // rows per chunk of the RHS kernel for an instance launched with `waves`
 // wavefronts per chunk row in total
-int rhs_rows(int nr, int P, long long waves_per_chunk_row);
+int rhs_rows(int nr, int P, long long waves_per_chunk_row, bool fp32);
 // the default segment shape of the radial solve, and whether shape `code`
 // is compiled and covers nr - 2 unknowns
 int solve_segment_rows(int nr);

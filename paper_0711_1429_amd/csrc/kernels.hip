@@ -599,12 +599,12 @@ __global__ __launch_bounds__(NT) void k_zfwd(const InstDev* __restrict__ I, int 
 // stencil points in increasing r, forms the per-point operands of every
 // compact family once, and scatters them into the accumulators of the five
 // rows whose stencil contains the point.  Row cc of the chunk lives in
-// accumulator slot cc mod 5: its first point assigns the slot, its fifth
-// finishes it and the row is written at once, so five rows of accumulators
-// are live.  The point loop is unrolled by the slot period only (rr + 4 is a
-// multiple of 5), which keeps the kernel small enough for the instruction
-// cache; slots of rows outside the chunk collect values that are never
-// written.  Every chunk is full length: the last one is shifted down to end at
+// accumulator slot (cc + pad) mod 5: its first point assigns the slot, its
+// fifth finishes it and the row is written at once, so five rows of
+// accumulators are live.  The point loop is unrolled by the slot period only,
+// which keeps the kernel small enough for the instruction cache; when the
+// rr + 4 points are not whole periods the walk starts pad < 5 points early.
+// Slots of rows outside the chunk collect values that are never written.  Every chunk is full length: the last one is shifted down to end at
 // row nr-3 and may recompute rows of its neighbour, writing bit-identical
 // values (the kernel reads nothing it writes).  The first chunk also writes
 // the off-centre eta row 1 and the zero row 0, the last chunk the eta row
@@ -831,21 +831,25 @@ __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, con
     const size_t S = (size_t)nr * P;
     const size_t fs = (size_t)nr * 5;
     const double bdt = sc.beta * dt * nu;
-    const int T = rr + 4;  // points, a multiple of 5
+    const int T = rr + 4;             // stencil points of the chunk
+    const int pad = (5 - T % 5) % 5;  // leading points that bring the walk to whole periods
     RhsAcc A[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) A[q] = RhsAcc{{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     RhsAcc W1 = {{0, 0}, {0, 0}, {0, 0}, {0, 0}}, W2 = W1;  // eta rows 1 and nr-2
     RhsPoint<TP> nxt;
-    rhs_load<TP>(v, eta, dv, ps, S, (size_t)(n0 - 2) * P + mode, nxt);
+    rhs_load<TP>(v, eta, dv, ps, S, (size_t)max(n0 - 2 - pad, 0) * P + mode, nxt);
     cd pv = {0, 0}, pe = {0, 0};
-    for (int base = 0; base < T; base += 5) {
+    // point mi = base + q - pad; the pad leading points (mi < 0, rows read
+    // clamped to the grid) only feed accumulators of rows before the chunk,
+    // which are never written, so row cc sits in slot (cc + pad) mod 5
+    for (int base = 0; base < T + pad; base += 5) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const int mi = base + q;
+            const int mi = base + q - pad;
             const int m = n0 - 2 + mi;  // <= n0 + rr + 1 <= nr - 1
             const RhsPoint<TP> cur = nxt;
-            rhs_load<TP>(v, eta, dv, ps, S, (size_t)min(m + 1, nr - 1) * P + mode, nxt);
+            rhs_load<TP>(v, eta, dv, ps, S, (size_t)min(max(m + 1, 0), nr - 1) * P + mode, nxt);
             // N_prev of the row finished at the next point (clamped row
             // index: the first three points read a row that is not used)
             cd npv = {0, 0}, npe = {0, 0};
@@ -854,7 +858,7 @@ __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, con
                 npv = widen<TP>(pnv[gid]);
                 npe = widen<TP>(pne[gid]);
             }
-            const RhsOps o = rhs_ops<TP>(cur, r[m], mm, al, nu, bdt);
+            const RhsOps o = rhs_ops<TP>(cur, r[max(m, 0)], mm, al, nu, bdt);
 #pragma unroll
             for (int jj = 0; jj < 5; ++jj) {
                 // row cc = mi - jj in slot (q - jj) mod 5; coefficient rows
@@ -865,15 +869,15 @@ __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, con
                 rhs_acc_both(A[slot], o, coef + (size_t)n * 5 + jj, fs, bdt);
                 pin_both(A[slot]);
             }
-            if (base == 0) {  // sigma_1 = 0: points 0..4 of the first chunk
-                rhs_acc_eta(W1, o, coef + 1 * 5 + q, fs, bdt);
+            if (mi >= 0 && mi < 5) {  // sigma_1 = 0: points 0..4 of the first chunk
+                rhs_acc_eta(W1, o, coef + 1 * 5 + mi, fs, bdt);
                 pin_eta(W1);
             }
-            if (base == T - 5) {  // sigma_{nr-2} = nr - 5: the last five points of the last chunk
-                rhs_acc_eta(W2, o, coef + (size_t)(nr - 2) * 5 + q, fs, bdt);
+            if (mi >= T - 5) {  // sigma_{nr-2} = nr - 5: the last five points of the last chunk
+                rhs_acc_eta(W2, o, coef + (size_t)(nr - 2) * 5 + (mi - (T - 5)), fs, bdt);
                 pin_eta(W2);
             }
-            if (q == 4 || base > 0)  // row mi - 4 is complete
+            if (mi >= 4)  // row mi - 4 is complete
                 rhs_store<TP, K>(nnv, nne, rv, re, (size_t)(n0 + mi - 4) * P + mode, true, A[(q + 1) % 5], pv, pe, dt,
                              sc);
             pv = npv;
@@ -895,12 +899,14 @@ __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, con
     }
 }
 
-// rows per chunk: rr + 4 must be a multiple of 5 and rr <= nr - 4.  The
-// longest such chunk up to RHS_MAX_ROWS re-reads the least halo; small
-// launches (a few hundred wavefronts) take shorter chunks, trading halo
-// re-reads for wavefronts in flight.
+// rows per chunk (1 <= rr <= nr - 4).  Large FP64 launches take one chunk
+// per column.  Otherwise the default takes rr + 4 a multiple of 5 (no
+// leading points): the longest such chunk up to RHS_MAX_ROWS re-reads the
+// least halo; small launches (a few hundred wavefronts) take shorter chunks,
+// trading halo re-reads for wavefronts in flight.
 constexpr int RHS_MAX_ROWS = 21;
 constexpr int RHS_MIN_WAVES = 4096;
+constexpr long long RHS_ONE_CHUNK_WAVES = 1000;
 
 template <typename TP, int K>
 __global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepCoef sc) {
@@ -2068,7 +2074,10 @@ void launch_zfwd(const Batch& B, bool fp32, hipStream_t s) {
         hipLaunchKernelGGL(k_zfwd<double>, grid, dim3(NT), (size_t)jb * g.nz * sizeof(C<double>), s, B.inst, jb);
 }
 
-int rhs_rows(int nr, int P, long long waves_per_chunk_row) {
+int rhs_rows(int nr, int P, long long waves_per_chunk_row, bool fp32) {
+    // FP64 launches with a thousand or more wavefronts per chunk row walk each
+    // column in one chunk (no halo; measured fastest at 129 x 65280 modes)
+    if (!fp32 && waves_per_chunk_row >= RHS_ONE_CHUNK_WAVES) return nr - 4;
     const int cap = min(nr - 4, RHS_MAX_ROWS);
     int rr = cap - ((cap - 1) % 5);
     (void)P;

@@ -357,7 +357,7 @@ int build_classes(tc_ctx* c) {
     // RHS chunk length per instance, from the wavefronts of one launch over all instances
     long long rhs_waves = 0;
     for (auto& in : c->inst) rhs_waves += (in.g.P + 63) / 64;
-    for (auto& in : c->inst) in.g.rhs_rr = rhs_rows(in.g.nr, in.g.P, rhs_waves);
+    for (auto& in : c->inst) in.g.rhs_rr = rhs_rows(in.g.nr, in.g.P, rhs_waves, c->fp32);
     // launch groups per stage, keyed by stage_key; extents are the members' largest
     for (int st = 0; st < ST_COUNT; ++st) {
         auto& G = c->groups[st];
@@ -912,17 +912,28 @@ int tc_autotune(tc_ctx* c, int repeats) {
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(c, TC_EDEVICE, "hipEventCreate");
     const int k = 1;  // a substep that reads and writes the N registers
     if (!rc) rc = run_substep(c, k);
-    // RHS rows per chunk, per launch group
+    // RHS chunks per column, per launch group: with n chunks every member takes
+    // rr = ceil((nr - 4) / n) rows per chunk (the last chunk overlaps its
+    // neighbour by less than n rows); the group's grid is sized by the
+    // largest nr and the smallest rr, and lanes past a member's chunks return
     for (auto& gr : c->groups[ST_RHS]) {
         if (rc) break;
-        int best_rr = -1;
+        std::vector<int> best_rr;
         double best = 1e30;
-        for (int rr : {21, 16, 11, 6}) {
+        // candidates: n chunks per member (n > 0), or -n rows for every member
+        for (int cand : {1, 2, 3, 4, 5, 6, 8, 10, -21, -16, -11, -6}) {
+            std::vector<int> rr;
+            int rr_min = 1 << 30;
             bool ok = true;
-            for (int i : gr.members) ok = ok && rr <= c->inst[i].g.nr - 4;
+            for (int i : gr.members) {
+                const int rows = c->inst[i].g.nr - 4;
+                rr.push_back(cand > 0 ? (rows + cand - 1) / cand : -cand);
+                ok = ok && rr.back() <= rows;
+                rr_min = std::min(rr_min, rr.back());
+            }
             if (!ok) continue;
-            for (int i : gr.members) c->inst[i].g.rhs_rr = rr;
-            gr.g.rhs_rr = rr;
+            for (size_t m = 0; m < gr.members.size(); ++m) c->inst[gr.members[m]].g.rhs_rr = rr[m];
+            gr.g.rhs_rr = rr_min;
             if ((rc = upload_descriptors(c))) break;
             double ms = 0;
             if ((rc = time_stage(c, ST_RHS, gr, k, repeats, e0, e1, &ms))) break;
@@ -932,12 +943,12 @@ int tc_autotune(tc_ctx* c, int repeats) {
             }
         }
         if (rc) break;
-        if (best_rr > 0) {
-            for (int i : gr.members) c->inst[i].g.rhs_rr = best_rr;
-            gr.g.rhs_rr = best_rr;
+        int rr_min = 1 << 30;
+        for (size_t m = 0; m < gr.members.size(); ++m) {
+            c->inst[gr.members[m]].g.rhs_rr = best_rr[m];
+            rr_min = std::min(rr_min, best_rr[m]);
         }
-        // groups whose members are too short for every candidate keep their rows
-        for (int i : gr.members) gr.g.rhs_rr = std::min(gr.g.rhs_rr, c->inst[i].g.rhs_rr);
+        gr.g.rhs_rr = rr_min;
     }
     // segment shape of the radial solve, per launch group
     for (auto& gr : c->groups[ST_SOLVE]) {
@@ -968,6 +979,26 @@ int tc_autotune(tc_ctx* c, int repeats) {
     if (e1) (void)hipEventDestroy(e1);
     cleanup();
     return rc;
+}
+
+int tc_set_rhs_rows(tc_ctx* c, int inst, int rows) {
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (rows < 1 || rows > in->g.nr - 4) return fail(c, TC_EINVAL, "rows per chunk must be in [1, nr - 4]");
+    if (int rc = need_device(c)) return rc;
+    in->g.rhs_rr = rows;
+    // the launch group's grid covers its members with the smallest chunk
+    for (auto& gr : c->groups[ST_RHS]) {
+        bool member = false;
+        int rr_min = 1 << 30;
+        for (int i : gr.members) {
+            member = member || i == inst;
+            rr_min = std::min(rr_min, c->inst[i].g.rhs_rr);
+        }
+        if (member) gr.g.rhs_rr = rr_min;
+    }
+    drop_graph(c);
+    return upload_descriptors(c);
 }
 
 int tc_tuning(const tc_ctx* cc, int inst, int* rhs_rows_out, int* solve_shape_out) {

@@ -76,6 +76,7 @@ _SIGNATURES = {
     "tc_velocity": (ctypes.c_int, [_P, ctypes.c_int, _D, _D]),
     "tc_products": (ctypes.c_int, [_P, ctypes.c_int, _D]),
     "tc_profiles": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "tc_set_rhs_rows": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "tc_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TcStats)]),
     "tc_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -233,6 +234,9 @@ class Solver:
 
     def autotune(self, repeats=5):
         self._check(self.lib.tc_autotune(self.ctx, int(repeats)))
+
+    def set_rhs_rows(self, rows, inst=0):
+        self._check(self.lib.tc_set_rhs_rows(self.ctx, inst, int(rows)))
 
     def tuning(self, inst=0):
         rr, sh = ctypes.c_int(), ctypes.c_int()

@@ -316,6 +316,38 @@ def test_mixed_products_at_turbulent_size():
         del m
 
 
+@pytest.mark.parametrize("name", ["tc-small-fp64", "tc-medium-fp64"])
+def test_rhs_chunking_is_bit_identical(name):
+    """The explicit-term kernel walks each radial column in chunks; every row's
+    terms are summed in the same order whatever the chunk length, including
+    lengths whose rr + 4 points are not whole periods of the rolled loop (the
+    walk then starts up to 4 points early).  One step for each chunk length
+    gives the default's state bit for bit, in both precisions."""
+    from tests.helpers import abi_geometry, fields_for
+    w = workload(name)
+    for prec in (tcb.TC_PREC_FP64, tcb.TC_PREC_MIXED):
+        ref = tcb.Solver(abi_geometry(w, prec))
+        f = fields_for(w, ref.grid())
+        ref.load_fields(*f)
+        ref.step(1)
+        want = ref.get_fields()
+        nr = ref.mode_shape()[0]
+        rows = sorted({1, 2, 3, 4, 7, 13, 22, 25, (nr - 4 + 1) // 2, nr - 4} & set(range(1, nr - 3)))
+        g = tcb.Solver(abi_geometry(w, prec))
+        for rr in rows:
+            g.set_rhs_rows(rr)
+            assert g.tuning()["rhs_rows"] == rr
+            g.load_fields(*f)
+            g.step(1)
+            got = g.get_fields()
+            for a, b, k in zip(got, want, ("v", "eta", "u_mean", "w_mean")):
+                assert np.array_equal(a, b), (name, prec, rr, k)
+        with pytest.raises(tcb.TcError):
+            g.set_rhs_rows(nr - 3)
+        with pytest.raises(tcb.TcError):
+            g.set_rhs_rows(0)
+
+
 def test_graph_replays_match_eager_steps():
     """Whole-step graph replays, with eager work (field reads) and
     synchronisation between them, give bit-identical states to eager launches."""
