@@ -1548,17 +1548,19 @@ struct DevSync {
     __device__ __forceinline__ void operator()() const { __syncthreads(); }
 };
 
-constexpr int zlane_cols(int N) {
-    const int c = 3072 / N;
+// j-columns per block of the z kernels: 3072 complex doubles or 6144
+// complex floats per tile (48 KiB of LDS), at most 16 columns
+constexpr int zlane_cols(int N, int esize) {
+    const int c = (esize == 8 ? 6144 : 3072) / N;
     return c < 1 ? 1 : (c > 16 ? 16 : c);
 }
 
 // Column pitch of the z kernels' LDS tiles: the transposes read or write one
 // element per column for consecutive columns, so the pitch is offset from N
-// by 16 / JB elements (16-byte slots), which puts the JB columns of a group of
-// 16 lanes on distinct banks.
-constexpr int zlane_pitch(int N) {
-    const int jb = zlane_cols(N);
+// by 16 / JB elements, which puts the JB columns of a group of 16 lanes in
+// distinct element slots (and so spreads them over the banks).
+constexpr int zlane_pitch(int N, int esize) {
+    const int jb = zlane_cols(N, esize);
     return N + ((16 % jb) == 0 ? 16 / jb : 1);
 }
 
@@ -1730,7 +1732,7 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
 // inverse z transform of u, v, w for JB j-columns of one plane; v, eta and
 // D v are read once per element.
 template <typename T, int N>
-__global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane(const InstDev* __restrict__ I) {
+__global__ __launch_bounds__(zlane_cols(N, sizeof(C<T>)) * lane::Plan<N>::TL) void k_zinv_lane(const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
     const auto* __restrict__ v = glb(b.v);
@@ -1740,7 +1742,7 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
     const auto* __restrict__ wmean = glb(b.wmean);
     auto* __restrict__ zb = glb((C<T>*)b.zb);
     using PL = lane::Plan<N>;
-    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL, PITCH = zlane_pitch(N);
+    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N, sizeof(C<T>)), NTH = JB * TL, PITCH = zlane_pitch(N, sizeof(C<T>));
     __shared__ C<T> lds[JB * PITCH];
     const int c = threadIdx.x / TL;
     const int gl = threadIdx.x - c * TL;
@@ -1832,13 +1834,13 @@ __global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zinv_lane
 // forward z transform of the six products for JB j-columns of one plane,
 // truncation to |l| <= K_z and normalisation.
 template <typename T, int N>
-__global__ __launch_bounds__(zlane_cols(N) * lane::Plan<N>::TL) void k_zfwd_lane(const InstDev* __restrict__ I) {
+__global__ __launch_bounds__(zlane_cols(N, sizeof(C<T>)) * lane::Plan<N>::TL) void k_zfwd_lane(const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
     const auto* __restrict__ pb = glb((const C<T>*)b.pb);
     auto* __restrict__ ps = glb((C<T>*)b.ps);
     using PL = lane::Plan<N>;
-    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N), NTH = JB * TL, PITCH = zlane_pitch(N);
+    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N, sizeof(C<T>)), NTH = JB * TL, PITCH = zlane_pitch(N, sizeof(C<T>));
     __shared__ C<T> lds[JB * PITCH];
     const int c = threadIdx.x / TL;
     const int gl = threadIdx.x - c * TL;
@@ -1967,13 +1969,13 @@ void launch_dv(const Batch& B, hipStream_t s) {
 
 template <typename T, int N>
 void zinv_lane(const Batch& B, hipStream_t s) {
-    constexpr int JB = zlane_cols(N);
+    constexpr int JB = zlane_cols(N, sizeof(C<T>));
     dim3 grid((B.g.nj + JB - 1) / JB, B.g.nr, B.count);
     hipLaunchKernelGGL((k_zinv_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, B.inst);
 }
 template <typename T, int N>
 void zfwd_lane(const Batch& B, hipStream_t s) {
-    constexpr int JB = zlane_cols(N);
+    constexpr int JB = zlane_cols(N, sizeof(C<T>));
     dim3 grid((B.g.nj + JB - 1) / JB, B.g.nr, B.count);
     hipLaunchKernelGGL((k_zfwd_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, B.inst);
 }
