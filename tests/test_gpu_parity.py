@@ -386,6 +386,9 @@ def test_batched_instances_equal_single_runs():
             one.step(3)
             for x, y in zip(multi.get_fields(i), one.get_fields()):
                 assert np.array_equal(x, y), (prec, i)
+            pm, ps_ = multi.profiles(i), one.profiles()
+            for k in pm:
+                assert np.array_equal(pm[k], ps_[k]), (prec, i, k)
     orc, _ = pair(ws[0])
     orc.step(3)
     multi = tcb.Solver([abi_geometry(w) for w in ws])
