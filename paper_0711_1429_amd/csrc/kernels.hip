@@ -297,7 +297,10 @@ __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __re
     const DevBuf b = I[blockIdx.z].b;
     const auto* __restrict__ v = glb(b.v);
     auto* __restrict__ dv = glb(b.dv);
+    // segment end values: forward sweep (xc) and back substitution (xb) in
+    // separate arrays, so the second exchange needs no barrier before it
     __shared__ cd xc[DV_SEGMENTS][2][64];
+    __shared__ cd xb[DV_SEGMENTS][2][64];
     if ((int)blockIdx.x * 64 >= g.P) return;  // past this instance's modes (whole block)
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x & 63;
@@ -362,7 +365,6 @@ __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __re
 #pragma unroll
     for (int i = 0; i < L; ++i)
         if (i < len) p[i] = cfma(hf1[s0 + i], c1, cfma(hf2[s0 + i], c2, p[i]));
-    __syncthreads();  // xc is reused
     {
         cd q1 = {0, 0}, q2 = {0, 0};
 #pragma unroll
@@ -378,16 +380,16 @@ __global__ __launch_bounds__(64 * DV_SEGMENTS) void k_dv_seg(const InstDev* __re
         }
     }
     // backward carries: (x_{t0}, x_{t0+1}) of segment t with zero carry-in
-    xc[seg][0][lane] = p[0];
-    xc[seg][1][lane] = p[1];
+    xb[seg][0][lane] = p[0];
+    xb[seg][1][lane] = p[1];
     __syncthreads();
     cd d1c = {0, 0}, d2c = {0, 0};  // x_{s1}, x_{s1+1}; zero beyond the last non-empty segment
     if (!act || len == 0) return;
     for (int t = DV_SEGMENTS - 1; t > seg; --t) {
         const int t0 = 2 + t * L;
         if (t0 >= nr - 2) continue;  // empty segment: carries pass through
-        const cd n1 = cfma(hb1[t0], d1c, cfma(hb2[t0], d2c, xc[t][0][lane]));
-        const cd n2 = cfma(hb1[t0 + 1], d1c, cfma(hb2[t0 + 1], d2c, xc[t][1][lane]));
+        const cd n1 = cfma(hb1[t0], d1c, cfma(hb2[t0], d2c, xb[t][0][lane]));
+        const cd n2 = cfma(hb1[t0 + 1], d1c, cfma(hb2[t0 + 1], d2c, xb[t][1][lane]));
         d1c = n1;
         d2c = n2;
     }
@@ -1204,8 +1206,13 @@ template <int L, int SV_SEGMENTS>
 __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* __restrict__ I, int k) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
-    __shared__ cd xc[SV_SEGMENTS][2][64];      // end values of each segment
-    __shared__ double hx[SV_SEGMENTS][4][64];  // end responses of each segment
+    // end values and end responses of each segment, forward sweep (xc, hx)
+    // and back substitution (xb, hb) in separate arrays, so the second
+    // exchange needs no barrier before it
+    __shared__ cd xc[SV_SEGMENTS][2][64];
+    __shared__ double hx[SV_SEGMENTS][4][64];
+    __shared__ cd xb[SV_SEGMENTS][2][64];
+    __shared__ double hb[SV_SEGMENTS][4][64];
     if ((int)blockIdx.x * 64 >= g.P) return;  // past this instance's modes (whole block)
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x & 63;
@@ -1292,7 +1299,6 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
         for (int i = 0; i < L; ++i)
             if (i < len) y[i] = cfma(h1[i], c1, cfma(h2[i], c2, y[i]));
     }
-    __syncthreads();  // xc, hx are reused
     // back substitution from zero carry-in, with the responses to x_{s1}, x_{s1+1}
     {
         cd q1 = {0, 0}, q2 = {0, 0};
@@ -1319,19 +1325,19 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
     }
     // (x_{s0}, x_{s0+1}) from zero carry-in; for a one-row segment x_{s0+1} is
     // the carried-in x_{s1} itself, which is zero for the last segment
-    xc[seg][0][lane] = y[0];
-    xc[seg][1][lane] = y[1];
-    hx[seg][0][lane] = h1[0];
-    hx[seg][1][lane] = h2[0];
-    hx[seg][2][lane] = h1[1];
-    hx[seg][3][lane] = h2[1];
+    xb[seg][0][lane] = y[0];
+    xb[seg][1][lane] = y[1];
+    hb[seg][0][lane] = h1[0];
+    hb[seg][1][lane] = h2[0];
+    hb[seg][2][lane] = h1[1];
+    hb[seg][3][lane] = h2[1];
     __syncthreads();
     if (!act || len == 0) return;
     cd d1 = {0, 0}, d2 = {0, 0};  // x_{s1}, x_{s1+1}: zero beyond the last non-empty segment
     for (int t = SV_SEGMENTS - 1; t > seg; --t) {
         if (1 + t * L >= nr - 1) continue;  // empty segment
-        const cd n1 = cfma(hx[t][0][lane], d1, cfma(hx[t][1][lane], d2, xc[t][0][lane]));
-        const cd n2 = cfma(hx[t][2][lane], d1, cfma(hx[t][3][lane], d2, xc[t][1][lane]));
+        const cd n1 = cfma(hb[t][0][lane], d1, cfma(hb[t][1][lane], d2, xb[t][0][lane]));
+        const cd n2 = cfma(hb[t][2][lane], d1, cfma(hb[t][3][lane], d2, xb[t][1][lane]));
         d1 = n1;
         d2 = n2;
     }
