@@ -24,9 +24,8 @@ What it computes (paper section / equation it follows):
                   the mean (0,0) mode (Sec. 4; Appendix).
 * ``stepper``  -- the 3-substep low-storage Runge--Kutta / Crank--Nicolson
                   substep (Sec. 2.1; Sec. 3.1; Sec. 4).
-* ``stats``    -- torque (eq. (torque), Table 2), wall shear, Re_tau (Sec. 5)
-                  and kinetic energy.
-* ``banded``   -- banded assembly helpers.
+* ``stats``    -- torque (eq. (torque), Table 2), wall shear, Re_tau (Sec. 5),
+                  kinetic energy and radial profiles.
 
 Every function is FP64 and vectorised only over Fourier modes; there is no
 blocking, fusion or reordering beyond the definitions it follows.  Where the

@@ -113,9 +113,11 @@ struct StepCoef {
 struct DevBuf {
     C<double>* v;
     C<double>* eta;
-    void* nv[2];       // explicit-term registers of v, alternating by substep (mean slot:
-                       // mean axial); complex of the transform precision
-    void* neta[2];     // the same for eta (mean slot: mean azimuthal)
+    void* nv[2];       // explicit-term registers of v, alternating by substep (mean slot
+                       // unused); complex of the transform precision
+    void* neta[2];     // the same for eta (mean slot unused)
+    double* nmean;     // [2][2][nr] explicit terms of the mean axial and azimuthal
+                       // profiles, alternating like nv/neta; FP64 in both precisions
     C<double>* dv;     // radial derivative of v
     C<double>* rv;     // right-hand side / forward-elimination values of v
     C<double>* re;     // the same for eta

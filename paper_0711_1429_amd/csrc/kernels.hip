@@ -652,17 +652,17 @@ __device__ __forceinline__ void rhs_mean_row(const DevGeom& g, const DevBuf& b, 
         }
         double pu = 0.0, pw = 0.0;
         if (K > 0) {
-            pu = (double)((const C<TP>*)b.nv[K - 1])[gid].x;
-            pw = (double)((const C<TP>*)b.neta[K - 1])[gid].x;
+            pu = b.nmean[((size_t)(K - 1) * 2 + 0) * nr + n];
+            pw = b.nmean[((size_t)(K - 1) * 2 + 1) * nr + n];
         }
         rv.x = iu + g.dt * (sc.gamma * fu + sc.rho * pu);
         re.x = iw + g.dt * (sc.gamma * fw + sc.rho * pw);
         fnu.x = fu;
         fnw.x = fw;
     }
-    if (K < 2) {
-        ((C<TP>*)b.nv[K])[gid] = C<TP>{(TP)fnu.x, (TP)0};
-        ((C<TP>*)b.neta[K])[gid] = C<TP>{(TP)fnw.x, (TP)0};
+    if (K < 2) {  // the mean flow's explicit terms stay FP64 in both precisions
+        b.nmean[((size_t)K * 2 + 0) * nr + n] = fnu.x;
+        b.nmean[((size_t)K * 2 + 1) * nr + n] = fnw.x;
     }
     b.rv[gid] = rv;
     b.re[gid] = re;

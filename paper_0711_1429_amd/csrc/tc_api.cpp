@@ -258,6 +258,8 @@ int alloc_instance(tc_ctx* c, Instance& in) {
         b.nv[q] = nreg + (size_t)(2 * q) * S * cz;
         b.neta[q] = nreg + (size_t)(2 * q + 1) * S * cz;
     }
+    if ((rc = dev_alloc(c, in, &b.nmean, (size_t)4 * s.nr))) return rc;
+    HIPCHK(c, hipMemset(b.nmean, 0, (size_t)4 * s.nr * sizeof(double)));
     if ((rc = dev_alloc(c, in, &b.umean, s.nr))) return rc;
     if ((rc = dev_alloc(c, in, &b.wmean, s.nr))) return rc;
     char* raw = nullptr;
@@ -658,6 +660,7 @@ int tc_load_fields(tc_ctx* c, int inst, const double* v, const double* eta, cons
         HIPCHK(c, hipMemsetAsync(in->b.nv[q], 0, S * cz, s));
         HIPCHK(c, hipMemsetAsync(in->b.neta[q], 0, S * cz, s));
     }
+    HIPCHK(c, hipMemsetAsync(in->b.nmean, 0, (size_t)4 * in->s.nr * sizeof(double), s));
     HIPCHK(c, hipStreamSynchronize(s));
     in->time = 0.0;
     in->steps = 0;
@@ -773,16 +776,12 @@ int tc_profiles(tc_ctx* c, int inst, double* out) {
     return TC_OK;
 }
 
-int tc_stats(tc_ctx* c, int inst, tc_stats_t* out) {
-    Instance* in = get_inst(c, inst);
-    if (!in || !out) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
-    if (int rc = need_device(c)) return rc;
-    timed(c, K_DV, [&] { launch_dv(batch_of(*in), c->stream); });
-    timed(c, K_ENERGY, [&] { launch_stats(in->g, in->b, c->stream); });
-    if (int rc = check_launch(c, "stats")) return rc;
-    double st[5];
-    HIPCHK(c, hipMemcpyAsync(st, in->b.stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+namespace {
+
+// The statistics of instance `in` from the 5 reduction results st (wall
+// shear g at both walls, energy sums with and without the mean, non-finite
+// flag).
+void fill_stats(const Instance* in, const double st[5], tc_stats_t* out) {
     const Setup& s = in->s;
     double vol = 0.0;
     for (int n = 0; n < s.nr; ++n) {
@@ -803,6 +802,21 @@ int tc_stats(tc_ctx* c, int inst, tc_stats_t* out) {
     out->energy_pert = st[3] / (2.0 * vol);
     out->steps = in->steps;
     out->nonfinite = st[4] != 0.0;
+}
+
+}  // namespace
+
+int tc_stats(tc_ctx* c, int inst, tc_stats_t* out) {
+    Instance* in = get_inst(c, inst);
+    if (!in || !out) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    timed(c, K_DV, [&] { launch_dv(batch_of(*in), c->stream); });
+    timed(c, K_ENERGY, [&] { launch_stats(in->g, in->b, c->stream); });
+    if (int rc = check_launch(c, "stats")) return rc;
+    double st[5];
+    HIPCHK(c, hipMemcpyAsync(st, in->b.stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    fill_stats(in, st, out);
     return TC_OK;
 }
 
@@ -892,7 +906,8 @@ int tc_autotune(tc_ctx* c, int repeats) {
         const std::pair<void*, size_t> parts[] = {{in.b.v, S * 16}, {in.b.eta, S * 16},
                                                   {in.b.umean, in.s.nr * 8ul}, {in.b.wmean, in.s.nr * 8ul},
                                                   {in.b.nv[0], S * cz}, {in.b.neta[0], S * cz},
-                                                  {in.b.nv[1], S * cz}, {in.b.neta[1], S * cz}};
+                                                  {in.b.nv[1], S * cz}, {in.b.neta[1], S * cz},
+                                                  {in.b.nmean, in.s.nr * 32ul}};
         for (auto& pr : parts) {
             void* q = nullptr;
             if (hipMalloc(&q, pr.second) != hipSuccess) {

@@ -40,8 +40,11 @@ def _compare_state(orc, gpu, tol=TOL, label=""):
     # the mean axial flow is the (0,0) mode of u (it starts at zero and stays
     # tiny, so it is measured against the whole u field as the metric defines)
     errs["u_mean_in_u"] = float(np.linalg.norm(um - rum) / np.sqrt(np.sum(np.abs(u) ** 2)))
+    info = {}
+    if np.linalg.norm(rum) > 0:  # the mean axial flow against itself (reported)
+        info["u_mean_self"] = rel_l2(um, rum)
     bad = {k: x for k, x in errs.items() if not x <= tol}
-    print(label, {k: f"{x:.2e}" for k, x in errs.items()}, flush=True)
+    print(label, {k: f"{x:.2e}" for k, x in errs.items()}, {k: f"{x:.2e}" for k, x in info.items()}, flush=True)
     assert not bad, (label, bad)
     return errs
 
@@ -140,6 +143,21 @@ def test_ragged_and_degenerate_sizes(sizes, flags):
     _compare_state(orc, gpu, tol=TOL, label=str(sizes))
 
 
+@PATHS
+@pytest.mark.parametrize("nr", [131, 140])
+def test_radial_sweeps_beyond_the_segmented_shapes(nr, flags):
+    """N_r above the largest segmented shape of the solve (N_r - 2 > 128 rows)
+    and of the D v sweep (N_r > 132) takes the one-lane-per-column kernels
+    (k_solve_lu, k_dv): both against the oracle for three steps."""
+    w = workload("tc-small-fp64", nr=nr, ntheta=12, nz=24, amplitude=1e-2, stretch=1.2)
+    orc, gpu = pair(w, flags=flags)
+    assert gpu.tuning()["solve_shape"] == 0
+    for s in range(3):
+        orc.step(1)
+        gpu.step(1)
+        _compare_state(orc, gpu, label=f"nr={nr} step {s + 1}")
+
+
 @pytest.mark.parametrize("sizes", [dict(nr=9, ntheta=729, nz=192), dict(nr=9, ntheta=96, nz=384)])
 def test_mixed_precision_paired_column_groups(sizes):
     """Mixed precision where the FP32 z kernels pair their column groups
@@ -194,9 +212,16 @@ def test_turbulent_size_one_substep_sampled(flags):
     rng = np.random.default_rng(7)
     nmodes = orc.nmodes
     sample = rng.choice(np.flatnonzero(~orc.mc.is_mean), size=48, replace=False)
-    j0 = np.flatnonzero((orc.m_flat == 0) & (orc.alpha_flat != 0))[:2]
-    hi = [nmodes - 1, nmodes - 2]
-    sample = np.unique(np.concatenate([sample, j0, hi]))
+    # the lowest wavenumbers, whose mass operator carries the largest 1/k^2
+    # (j <= 2, |l| <= 2, both signs of l), and the highest
+    nl = orc.disc.nl
+    kz = (nl - 1) // 2
+    low = [j * nl + kz + l for j in range(3) for l in range(-2, 3) if (j, l) != (0, 0)]
+    hi = [nmodes - 1, nmodes - 2, 2 * kz, 0]  # (K_theta, K_z), (K_theta, K_z - 1), (0, +-K_z)
+    sample = np.unique(np.concatenate([sample, low, hi]))
+    assert not np.any(orc.mc.is_mean[sample])
+    assert np.min(np.hypot(orc.m_flat[sample], orc.alpha_flat[sample])) == np.min(
+        np.hypot(orc.m_flat, orc.alpha_flat)[~orc.mc.is_mean])
     vs, es = orc.substep_sample(0, sample)
     v, e, um, wm = gpu.get_fields()
     v = v.reshape(v.shape[0], -1)[:, sample]
