@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--precision", choices=("fp64", "mixed"), default=None,
                    help="default: fp64, or mixed for the batched workload")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the mixed-precision and batched sub-records of the default line")
     p.add_argument("--autotune", choices=("on", "off", "auto"), default="auto",
                    help="time the launch variants before the run (auto: on for the batched workload)")
     p.add_argument("--eager", action="store_true",
@@ -134,6 +136,16 @@ def cpu_baseline(w, nmodes_sample):
     }
 
 
+def method_bytes(w, precision):
+    """Minimum HBM bytes of one substep of the staged method: every stage
+    reads its inputs and writes its outputs once; FP64 448 S + 288 Q, mixed
+    (complex64 transform-side arrays) 304 S + 144 Q."""
+    kt, kz = (w["ntheta"] - 1) // 3, (w["nz"] - 1) // 3
+    S = w["nr"] * (kt + 1) * (2 * kz + 1)
+    Q = w["nr"] * w["nz"] * (kt + 1)
+    return (448.0 * S + 288.0 * Q) if precision == "fp64" else (304.0 * S + 144.0 * Q)
+
+
 def _rel(a, b, cj):
     return float(np.sqrt(np.sum(cj * np.abs(a - b) ** 2) / np.sum(cj * np.abs(b) ** 2)))
 
@@ -177,6 +189,144 @@ def accuracy(w, checkpoints):
     return out
 
 
+def _sync():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except ImportError:  # pragma: no cover
+        pass
+
+
+STEP_KERNELS = ("radial_derivative", "zfft_inverse", "theta_rows_products", "zfft_forward",
+                "radial_rhs", "radial_solve")
+
+
+def measure(workload, precision, steps, warmup, eager=False, autotune="auto"):
+    """Time `steps` whole RK3 steps of a workload (inputs resident in HBM):
+    first replayed from the captured step graph (the value), then launched
+    eagerly with HIP events around every kernel on the solver's stream (the
+    per-kernel figures)."""
+    from paper_0711_1429_amd import tc
+    from paper_0711_1429_amd.synth import WORKLOADS, batched_instances, initial_fields
+
+    batched = workload == "tc-batched-64"
+    ws = batched_instances() if batched else [dict(WORKLOADS[workload])]
+    prec = tc.TC_PREC_MIXED if precision == "mixed" else tc.TC_PREC_FP64
+    geos = [tc.make_geometry(zeta=w["zeta"], re=w["re"], nr=w["nr"], ntheta=w["ntheta"], nz=w["nz"],
+                             dt=w["dt"], stretch=w["stretch"], precision=prec) for w in ws]
+    solver = tc.Solver(geos)
+    if eager:
+        solver.use_graphs(False)
+    for i, w in enumerate(ws):
+        solver.load_fields(*initial_fields(solver.grid(i), w["zeta"], w["ntheta"], w["nz"], w["amplitude"],
+                                           w["seed"]), inst=i)
+    tuned = autotune == "on" or (autotune == "auto" and batched)
+    if tuned:
+        print(f"bench: {workload} autotune", file=sys.stderr, flush=True)
+        solver.autotune(5)
+    tuning = sorted({tuple(solver.tuning(i).items()) for i in range(len(ws))})
+    print(f"bench: {workload} {precision} warmup {warmup}", file=sys.stderr, flush=True)
+    solver.step(warmup)
+
+    # timed region 1 (the value): whole steps replayed from the captured graph
+    _sync()
+    t0 = time.perf_counter()
+    solver.step(steps)
+    _sync()
+    elapsed = time.perf_counter() - t0
+    # timed region 2 (per-kernel figures): the same steps launched eagerly,
+    # each launch bracketed by HIP events on the solver's stream
+    solver.timing(True)
+    _sync()
+    t1 = time.perf_counter()
+    solver.step(steps)
+    _sync()
+    elapsed_events = time.perf_counter() - t1
+    ktimes = solver.kernel_times()
+    solver.timing(False)
+    print(f"bench: {workload} {precision}: timed {steps} steps in {elapsed:.3f} s (graph), "
+          f"{elapsed_events:.3f} s (events)", file=sys.stderr, flush=True)
+
+    substeps = 3 * steps
+    pts = sum(w["nr"] * w["ntheta"] * w["nz"] for w in ws)
+    kbytes = {}
+    for i in range(len(ws)):
+        for name, bts in solver.kernel_bytes(i).items():
+            kbytes[name] = kbytes.get(name, 0.0) + bts
+    ncls = len({(w["nr"], w["ntheta"], w["nz"]) for w in ws})
+    per_kernel = {}
+    for name, (ms, calls) in ktimes.items():
+        if calls:
+            rec = {"avg_ms": ms / calls, "calls": calls}
+            if name in STEP_KERNELS:
+                # each step kernel is launched once per substep and launch
+                # group, covering every instance of the group: the algorithmic
+                # bytes of all instances over the summed launch time
+                rec["model_GBs"] = kbytes[name] * substeps / (ms * 1e-3) / 1e9
+            per_kernel[name] = rec
+    dom = max(STEP_KERNELS, key=lambda k: ktimes[k][0])
+    # whole-substep byte models.  method: each stage of the staged substep
+    # reads its inputs and writes its outputs in HBM once (448 S + 288 Q bytes
+    # in FP64, 304 S + 144 Q with complex64 transform-side arrays; S spectral
+    # and Q mixed-space points); implementation: the sum of the step kernels'
+    # own models, which also count this build's design traffic (the LU-factor
+    # table of the solve, the right-hand sides between the explicit-term and
+    # solve kernels, the separate D v array)
+    model = sum(method_bytes(w, precision) for w in ws)
+    impl = sum(kbytes[k] for k in STEP_KERNELS)
+    t_sub = elapsed / substeps
+    solver.close()
+    return {
+        "ws": ws, "batched": batched, "ncls": ncls, "pts": pts,
+        "value": pts * substeps / elapsed / 1e6,
+        "ms_per_step": elapsed / steps * 1e3,
+        "ms_per_step_events": elapsed_events / steps * 1e3,
+        "dominant": dom, "kbytes": kbytes, "kernels": per_kernel,
+        "substep_model": {"bytes": model, "ms_per_substep": t_sub * 1e3,
+                          "GBs": model / t_sub / 1e9, "frac": model / t_sub / 1e9 / HBM_PEAK_GBS,
+                          "implementation_bytes": impl,
+                          "implementation_frac": impl / t_sub / 1e9 / HBM_PEAK_GBS},
+        "launch_tuning": {"autotuned": tuned, "choices": [dict(t) for t in tuning]},
+    }
+
+
+def batched_accuracy(steps):
+    """The batched workload in mixed precision against the same instances in
+    FP64 after `steps` steps: the largest per-instance relative L2 error of
+    v, eta and w (mean included) and of the inner torque."""
+    from paper_0711_1429_amd import tc
+    from paper_0711_1429_amd.synth import batched_instances, initial_fields
+    ws = batched_instances()
+    out = {}
+    solvers = {}
+    for name, prec in (("fp64", tc.TC_PREC_FP64), ("mixed", tc.TC_PREC_MIXED)):
+        g = tc.Solver([tc.make_geometry(zeta=w["zeta"], re=w["re"], nr=w["nr"], ntheta=w["ntheta"], nz=w["nz"],
+                                        dt=w["dt"], stretch=w["stretch"], precision=prec) for w in ws])
+        for i, w in enumerate(ws):
+            g.load_fields(*initial_fields(g.grid(i), w["zeta"], w["ntheta"], w["nz"], w["amplitude"], w["seed"]),
+                          inst=i)
+        g.step(steps)
+        solvers[name] = g
+    worst = {"v": 0.0, "eta": 0.0, "w": 0.0, "torque_in": 0.0}
+    for i in range(len(ws)):
+        a, b = solvers["fp64"], solvers["mixed"]
+        v0, e0, _, _ = a.get_fields(i)
+        v1, e1, _, _ = b.get_fields(i)
+        cj = np.where(np.arange(v0.shape[1]) == 0, 1.0, 2.0)[None, :, None]
+        _, w0 = a.velocity(i)
+        _, w1 = b.velocity(i)
+        worst["v"] = max(worst["v"], _rel(v1, v0, cj))
+        worst["eta"] = max(worst["eta"], _rel(e1, e0, cj))
+        worst["w"] = max(worst["w"], _rel(w1, w0, cj))
+        worst["torque_in"] = max(worst["torque_in"], abs(b.stats(i)["torque_in"] / a.stats(i)["torque_in"] - 1))
+    for g in solvers.values():
+        g.close()
+    out["steps"] = steps
+    out["max_over_instances_mixed_vs_fp64"] = worst
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -193,116 +343,59 @@ def main():
         print(json.dumps({"workload": args.workload, "reference": "FP64 GPU path",
                           "mixed_vs_fp64": accuracy(w, cps)}), flush=True)
         return
-    from paper_0711_1429_amd import tc
-    from paper_0711_1429_amd.synth import WORKLOADS, batched_instances, initial_fields
-
     batched = args.workload == "tc-batched-64"
-    ws = batched_instances() if batched else [dict(WORKLOADS[args.workload])]
     precision = args.precision or ("mixed" if batched else "fp64")
-    prec = tc.TC_PREC_MIXED if precision == "mixed" else tc.TC_PREC_FP64
-    geos = [tc.make_geometry(zeta=w["zeta"], re=w["re"], nr=w["nr"], ntheta=w["ntheta"], nz=w["nz"],
-                             dt=w["dt"], stretch=w["stretch"], precision=prec) for w in ws]
-    solver = tc.Solver(geos)
-    if args.eager:
-        solver.use_graphs(False)
-    for i, w in enumerate(ws):
-        solver.load_fields(*initial_fields(solver.grid(i), w["zeta"], w["ntheta"], w["nz"], w["amplitude"],
-                                           w["seed"]), inst=i)
-    tuned = args.autotune == "on" or (args.autotune == "auto" and batched)
-    if tuned:
-        print("bench: autotune", file=sys.stderr, flush=True)
-        solver.autotune(5)
-    tuning = sorted({tuple(solver.tuning(i).items()) for i in range(len(ws))})
-    print(f"bench: {args.workload} {precision} warmup {args.warmup}", file=sys.stderr, flush=True)
-    solver.step(args.warmup)
-
-    try:
-        import torch
-        sync = torch.cuda.synchronize if torch.cuda.is_available() else (lambda: None)
-    except ImportError:  # pragma: no cover
-        sync = lambda: None  # noqa: E731
-
-    # timed region 1 (the value): whole steps replayed from the captured graph
-    sync()
-    t0 = time.perf_counter()
-    solver.step(args.steps)
-    sync()
-    elapsed = time.perf_counter() - t0
-    # timed region 2 (per-kernel figures): the same steps launched eagerly,
-    # each launch bracketed by HIP events on the solver's stream
-    solver.timing(True)
-    sync()
-    t1 = time.perf_counter()
-    solver.step(args.steps)
-    sync()
-    elapsed_events = time.perf_counter() - t1
-    ktimes = solver.kernel_times()
-    solver.timing(False)
-    print(f"bench: timed {args.steps} steps in {elapsed:.3f} s (graph), {elapsed_events:.3f} s (events)",
-          file=sys.stderr, flush=True)
-
-    substeps = 3 * args.steps
-    pts = sum(w["nr"] * w["ntheta"] * w["nz"] for w in ws)
-    value = pts * substeps / elapsed / 1e6
-    kbytes = {}
-    for i in range(len(ws)):
-        for name, bts in solver.kernel_bytes(i).items():
-            kbytes[name] = kbytes.get(name, 0.0) + bts
-    ncls = len({(w["nr"], w["ntheta"], w["nz"]) for w in ws})
-    per_kernel = {}
-    step_kernels = ("radial_derivative", "zfft_inverse", "theta_rows_products", "zfft_forward",
-                    "radial_rhs", "radial_solve")
-    for name, (ms, calls) in ktimes.items():
-        if calls:
-            rec = {"avg_ms": ms / calls, "calls": calls}
-            if name in step_kernels:
-                # each step kernel is launched once per substep and shape class,
-                # covering every instance of the class: the algorithmic bytes of
-                # all instances over the summed launch time of the pass
-                rec["model_GBs"] = kbytes[name] * substeps / (ms * 1e-3) / 1e9
-            per_kernel[name] = rec
-    dom = max(step_kernels, key=lambda k: ktimes[k][0])
-    achieved = per_kernel[dom]["model_GBs"]
-    # whole-substep byte model: each stage reads its inputs and writes its
-    # outputs in HBM once (the sum of the step kernels' algorithmic bytes)
-    model = sum(kbytes[k] for k in step_kernels)
-    t_sub = elapsed / substeps
-    w0 = ws[0]
-    config = ({"workload": args.workload, "instances": len(ws), "shape_classes": ncls, "precision": precision,
-               "total_points": pts}
+    m = measure(args.workload, precision, args.steps, args.warmup, args.eager, args.autotune)
+    ws, w0 = m["ws"], m["ws"][0]
+    config = ({"workload": args.workload, "instances": len(ws), "shape_classes": m["ncls"],
+               "precision": precision, "total_points": m["pts"]}
               if batched else
               {"workload": args.workload, "nr": w0["nr"], "ntheta": w0["ntheta"], "nz": w0["nz"],
                "zeta": w0["zeta"], "re": w0["re"], "dt": w0["dt"], "stretch": w0["stretch"],
                "precision": precision})
+    dom = m["dominant"]
+    achieved = m["kernels"][dom]["model_GBs"]
     out = {
         "metric": "Mpts*RK3 substeps/s on 1 GPU (FP64 vs mixed at stated L2 error); HBM GB/s",
-        "value": value,
+        "value": m["value"],
         "unit": "Mpts*substeps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == tc.TC_PREC_FP64 else "f32-transforms/f64-radial",
+        "dtype": "f64" if precision == "fp64" else "f32-transforms/f64-radial",
         "data": "synthetic: laminar Couette profile plus seeded random-phase divergence-free perturbation",
         "config": config,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes": kbytes[dom] / ncls,
+                     "algorithmic_bytes": m["kbytes"][dom] / m["ncls"],
                      "traffic": None if batched else measured_traffic(args.workload, precision, dom)},
-        "substep_model": {"bytes": model, "ms_per_substep": t_sub * 1e3,
-                          "GBs": model / t_sub / 1e9, "frac": model / t_sub / 1e9 / HBM_PEAK_GBS},
-        "ms_per_step_events": elapsed_events / args.steps * 1e3,
-        "launch_tuning": {"autotuned": tuned, "choices": [dict(t) for t in tuning]},
-        "kernels": per_kernel,
+        "substep_model": m["substep_model"],
+        "ms_per_step_events": m["ms_per_step_events"],
+        "launch_tuning": m["launch_tuning"],
+        "kernels": m["kernels"],
     }
-    w = w0
+    default_line = args.workload == "tc-turbulent-fp64" and precision == "fp64" and not args.eager
+    if default_line and not args.no_variants:
+        # the mixed-precision form on the same grid and the batched form, each
+        # timed the same way, with their errors against the FP64 path
+        mx = measure(args.workload, "mixed", args.steps, args.warmup)
+        out["mixed"] = {"value": mx["value"], "ms_per_step": mx["ms_per_step"],
+                        "speedup_vs_fp64": mx["value"] / m["value"],
+                        "substep_model": mx["substep_model"],
+                        "kernels": {k: v["avg_ms"] for k, v in mx["kernels"].items()},
+                        "accuracy_vs_fp64": accuracy(dict(w0), [1, 100, 1000])}
+        bt = measure("tc-batched-64", "mixed", args.steps, args.warmup)
+        out["batched"] = {"value": bt["value"], "ms_per_step": bt["ms_per_step"], "instances": len(bt["ws"]),
+                          "total_points": bt["pts"], "speedup_vs_fp64": bt["value"] / m["value"],
+                          "substep_model": bt["substep_model"], "launch_tuning": bt["launch_tuning"],
+                          "accuracy": batched_accuracy(100)}
     if not args.no_cpu_baseline and not batched:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_modes)
-    solver.close()
+        out["cpu_baseline"] = cpu_baseline(w0, args.cpu_modes)
     print(json.dumps(out), flush=True)
 
 
