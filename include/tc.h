@@ -199,6 +199,20 @@ int tc_stats(tc_ctx* ctx, int inst, tc_stats_t* out);
  * are always launched eagerly. */
 int tc_use_graphs(tc_ctx* ctx, int enable);
 
+/* tc_stats for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same statistics, from the same kernels in the same order (bit-identical
+ * results), with the reduction partials, flags and results in a static
+ * device array of the library (about 25 KB per GPU, held until the process
+ * ends; its address is looked up once per device by tc_create) instead of
+ * context-owned memory.  Makes no device allocation.  Limit: 1024 reduction
+ * blocks, which every grid fits (the reductions never use more); a larger
+ * need returns TC_EINVAL.  The context's device must be the current HIP
+ * device (else TC_EINVAL).  Every call on a GPU shares that GPU's array and
+ * overwrites what it reads: calls that overlap on one GPU (several threads or
+ * streams) race and must be serialised by the caller. */
+int tc_stats_noalloc(tc_ctx* ctx, int inst, tc_stats_t* out);
+
 /* Pick, by timing on the device, the launch parameters that do not change the
  * method: the rows per chunk of the explicit-term kernel (the columns split
  * into 1, 2, 3, 4, 5, 6, 8 or 10 chunks, each instance's rows divided evenly,

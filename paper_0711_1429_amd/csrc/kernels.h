@@ -193,6 +193,15 @@ void launch_velocity(const DevGeom& g, const DevBuf& b, C<double>* u, C<double>*
 void launch_stats(const DevGeom& g, const DevBuf& b, hipStream_t s);
 // radial profiles [6][nr] (mean u, mean w, <u'u'>, <v'v'>, <w'w'>, <v'w'>) into device memory out
 void launch_profiles(const DevGeom& g, const DevBuf& b, double* out, hipStream_t s);
+// The statistics with their reduction scratch in the library's file-scope
+// device array instead of b.partial / b.flags / b.stats.  noalloc_scratch_init
+// looks up that array's address on `device` (which must be current) once;
+// launch_stats_noalloc returns the device address of the 5 results, or null
+// when the device was not initialised or the grid needs more reduction blocks
+// than the array holds.
+hipError_t noalloc_scratch_init(int device);
+int noalloc_max_blocks();
+const double* launch_stats_noalloc(int device, const DevGeom& g, const DevBuf& b, hipStream_t s);
 // finite check of the state into b.flags[0]
 void launch_finite(const Batch& B, hipStream_t s);
 

@@ -24,6 +24,7 @@
 // The FFT stages are templated on the storage type (double, or float for the
 // mixed-precision path); recovery, the radial stages and reductions are FP64.
 #include <cmath>
+#include <mutex>
 
 #include "fft_lane.h"
 #include "kernels.h"
@@ -2161,6 +2162,58 @@ void launch_stats(const DevGeom& g, const DevBuf& b, hipStream_t s) {
     const int nb = reduction_blocks(g);
     hipLaunchKernelGGL(k_energy, dim3(nb), dim3(RED_NT), 0, s, g, b);
     hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(RED_NT), 0, s, g, b, nb);
+}
+
+// ------------------------------------------------ statistics without allocation
+// The reduction partials, flags and results of the statistics kernels in a
+// file-scope device array, for callers that cannot allocate device memory
+// (tc_stats_noalloc).  Every GPU the library runs on holds its own copy until
+// the process ends; its device address is looked up once per device, with
+// that device current, and host code uses only that address (the array's
+// name in host code is a host-side stand-in).  Layout, in doubles: partials
+// [2][kNoallocBlocks], flags [kNoallocBlocks] ints, results [16].  Every call
+// overwrites what it reads (each reduction block writes its own partial and
+// flag), so nothing needs clearing; calls that overlap on one GPU share the
+// array and race.
+constexpr int kNoallocBlocks = 1024;
+constexpr size_t kScratchDoubles = 2 * (size_t)kNoallocBlocks + kNoallocBlocks / 2 + 16;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    double* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+int noalloc_max_blocks() { return kNoallocBlocks; }
+
+const double* launch_stats_noalloc(int device, const DevGeom& g, const DevBuf& b, hipStream_t s) {
+    double* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (device >= 0 && device < kMaxDevices) base = g_scratch_ptr[device];
+    }
+    const int nb = reduction_blocks(g);
+    if (!base || nb > kNoallocBlocks) return nullptr;
+    DevBuf t = b;
+    t.partial = base;
+    t.flags = reinterpret_cast<int*>(base + 2 * (size_t)kNoallocBlocks);
+    t.stats = base + 2 * (size_t)kNoallocBlocks + kNoallocBlocks / 2;
+    t.partial_n = kNoallocBlocks;
+    launch_stats(g, t, s);
+    return t.stats;
 }
 
 // non-finite flag of every instance of a shape class into its stats[5]

@@ -82,6 +82,7 @@ struct tc_ctx {
     bool fp32 = false;
     hipStream_t own = nullptr;
     hipStream_t stream = nullptr;
+    int device = -1;                    // HIP device the context was created on
     std::string err;
     bool timing = false;
     std::vector<TimedLaunch> pending;
@@ -567,6 +568,12 @@ int tc_create(const tc_geometry* g, int n_instances, tc_ctx** out) {
             delete c;
             return fail(nullptr, TC_EDEVICE, std::string("libtc.so is built for gfx950, device is ") + prop.gcnArchName);
         }
+        c->device = dev;
+        // the static reduction scratch of tc_stats_noalloc: its address on this device
+        if (hipError_t e = noalloc_scratch_init(dev); e != hipSuccess) {
+            delete c;
+            return fail(nullptr, TC_EDEVICE, std::string("static scratch lookup failed: ") + hipGetErrorString(e));
+        }
         if (hipStreamCreate(&c->own) != hipSuccess) {
             delete c;
             return fail(nullptr, TC_EDEVICE, "hipStreamCreate failed");
@@ -815,6 +822,28 @@ int tc_stats(tc_ctx* c, int inst, tc_stats_t* out) {
     if (int rc = check_launch(c, "stats")) return rc;
     double st[5];
     HIPCHK(c, hipMemcpyAsync(st, in->b.stats, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    fill_stats(in, st, out);
+    return TC_OK;
+}
+
+int tc_stats_noalloc(tc_ctx* c, int inst, tc_stats_t* out) {
+    Instance* in = get_inst(c, inst);
+    if (!in || !out) return c ? fail(c, TC_EINVAL, "bad instance index or null pointer") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    if (reduction_blocks(in->g) > noalloc_max_blocks())
+        return fail(c, TC_EINVAL, "the grid needs " + std::to_string(reduction_blocks(in->g)) +
+                                      " reduction blocks; the static scratch holds " +
+                                      std::to_string(noalloc_max_blocks()));
+    int cur = -1;
+    HIPCHK(c, hipGetDevice(&cur));
+    if (cur != c->device) return fail(c, TC_EINVAL, "the context's device is not the current HIP device");
+    launch_dv(batch_of(*in), c->stream);
+    const double* res = launch_stats_noalloc(c->device, in->g, in->b, c->stream);
+    if (!res) return fail(c, TC_EDEVICE, "static scratch not initialised on this device");
+    if (int rc = check_launch(c, "stats (static scratch)")) return rc;
+    double st[5];
+    HIPCHK(c, hipMemcpyAsync(st, res, sizeof(st), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     fill_stats(in, st, out);
     return TC_OK;

@@ -78,6 +78,7 @@ _SIGNATURES = {
     "tc_profiles": (ctypes.c_int, [_P, ctypes.c_int, _D]),
     "tc_set_rhs_rows": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "tc_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TcStats)]),
+    "tc_stats_noalloc": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TcStats)]),
     "tc_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -227,6 +228,11 @@ class Solver:
     def stats(self, inst=0):
         s = TcStats()
         self._check(self.lib.tc_stats(self.ctx, inst, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in TcStats._fields_}
+
+    def stats_noalloc(self, inst=0):
+        s = TcStats()
+        self._check(self.lib.tc_stats_noalloc(self.ctx, inst, ctypes.byref(s)))
         return {name: getattr(s, name) for name, _ in TcStats._fields_}
 
     def use_graphs(self, enable):
