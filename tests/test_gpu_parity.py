@@ -37,12 +37,18 @@ def _compare_state(orc, gpu, tol=TOL, label=""):
     wp[:, 0, kz] = 0
     gwp[:, 0, kz] = 0
     errs["w_pert"] = rel_l2(gwp, wp)
-    # the mean axial flow is the (0,0) mode of u (it starts at zero and stays
-    # tiny, so it is measured against the whole u field as the metric defines)
+    # the mean axial flow is the (0,0) mode of u, measured also against the
+    # whole u field as the metric defines
     errs["u_mean_in_u"] = float(np.linalg.norm(um - rum) / np.sqrt(np.sum(np.abs(u) ** 2)))
     info = {}
-    if np.linalg.norm(rum) > 0:  # the mean axial flow against itself (reported)
-        info["u_mean_self"] = rel_l2(um, rum)
+    if np.linalg.norm(rum) > 0:
+        # the mean axial flow against itself: held to the FP64 bar; in mixed
+        # precision it carries the FP32 rounding of the products that force it
+        # and is only reported (it is part of u, which is held to the bar)
+        if tol <= TOL:
+            errs["u_mean_self"] = rel_l2(um, rum)
+        else:
+            info["u_mean_self"] = rel_l2(um, rum)
     bad = {k: x for k, x in errs.items() if not x <= tol}
     print(label, {k: f"{x:.2e}" for k, x in errs.items()}, {k: f"{x:.2e}" for k, x in info.items()}, flush=True)
     assert not bad, (label, bad)
