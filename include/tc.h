@@ -217,7 +217,9 @@ int tc_stats_noalloc(tc_ctx* ctx, int inst, tc_stats_t* out);
  * method: the rows per chunk of the explicit-term kernel (the columns split
  * into 1, 2, 3, 4, 5, 6, 8 or 10 chunks, each instance's rows divided evenly,
  * or 21, 16, 11 or 6 rows for every instance) and the segment shape of the
- * radial solve (8 x 4, 8 x 8 or 16 x 8 rows), per launch group.  Runs one substep to fill the intermediates, times `repeats`
+ * radial solve (8 x 4, 8 x 8 or 16 x 8 rows, each with one lane per mode or
+ * with the two signs of l of a wavenumber pair in the two halves of a
+ * wavefront), per launch group.  Runs one substep to fill the intermediates, times `repeats`
  * launches (1..1000) of each candidate and restores the state, the N
  * registers and the time exactly, so the fields are unchanged on return.
  * Allocates a temporary copy of the state (freed before returning).  The
@@ -235,8 +237,9 @@ int tc_set_rhs_rows(tc_ctx* ctx, int inst, int rows);
 
 /* The launch parameters in use for instance `inst` (after tc_create, or
  * after tc_autotune): rows per chunk of the explicit-term kernel, and the
- * solve's segment shape as 100 * segments + rows per segment (0: one lane
- * walks every row).  Either pointer may be NULL. */
+ * solve's segment shape as 100 * segments + rows per segment, plus 10000
+ * when the two signs of l of a pair share a wavefront (0: one lane walks
+ * every row).  Either pointer may be NULL. */
 int tc_tuning(const tc_ctx* ctx, int inst, int* rhs_rows, int* solve_shape);
 
 /* Per-kernel timing with HIP events on the context's stream.

@@ -88,7 +88,8 @@ struct DevGeom {
     int dv_seg;             // rows per segment of the segmented D v kernel, 0: sequential kernel
     int dv_nseg;            // segments of the segmented D v kernel
     int rhs_rr;             // rows per chunk of the RHS kernel
-    int solve_seg;          // segment shape of the radial solve (100 * segments + rows), 0: sequential
+    int solve_seg;          // segment shape of the radial solve (100 * segments + rows, + 10000 for
+                            // the paired lane layout), 0: sequential
     const double* m;        // [nj]
     const double* alpha;    // [nl]
     const double* tw_theta; // [ntheta] complex
@@ -180,9 +181,9 @@ long long stage_key(int stage, const DevGeom& g);
 // rows per chunk of the RHS kernel for an instance launched with `waves`
 // wavefronts per chunk row in total
 int rhs_rows(int nr, int P, long long waves_per_chunk_row, bool fp32);
-// the default segment shape of the radial solve, and whether shape `code`
-// is compiled and covers nr - 2 unknowns
-int solve_segment_rows(int nr);
+// the default segment shape and lane layout of the radial solve, and whether
+// shape `code` is compiled and covers nr - 2 unknowns
+int solve_segment_rows(int nr, int kz);
 bool solve_shape_fits(int code, int nr);
 // precomputed LU factors of substep k (run once per context and k)
 void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, hipStream_t s);

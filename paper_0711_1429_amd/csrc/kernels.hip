@@ -1203,7 +1203,16 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve_lu(const InstDev* __restrict
 // segments and corrects its rows; the back substitution runs the same way
 // from the last segment down.  Every right-hand side, factor and output is
 // read or written once, and all rows of a column are in flight together.
-template <int L, int SV_SEGMENTS>
+//
+// Lane layout.  Unpaired: lane i of block x takes mode 64 x + i of the plane.
+// Paired: block x takes the pairs (j, |l|) with |l| in 32 q .. 32 q + 31 of
+// one j (x = j * groups + q, groups = ceil((K_z + 1) / 32)); lane i < 32 takes
+// +|l| and lane 32 + i takes -|l| of the same pair, so the two lanes read the
+// pair's factors at the same address in the same instruction and each factor
+// is fetched once instead of once per sign of l.
+__device__ __forceinline__ int solve_pair_groups(int kz) { return (kz + 32) / 32; }
+
+template <int L, int SV_SEGMENTS, bool PAIRED>
 __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* __restrict__ I, int k) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
@@ -1214,22 +1223,37 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
     __shared__ double hx[SV_SEGMENTS][4][64];
     __shared__ cd xb[SV_SEGMENTS][2][64];
     __shared__ double hb[SV_SEGMENTS][4][64];
-    if ((int)blockIdx.x * 64 >= g.P) return;  // past this instance's modes (whole block)
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x & 63;
     const int eqn = blockIdx.y;
     const int nr = g.nr, kz = g.kz, nl = g.nl;
     const size_t P = g.P;
-    const int m0 = blockIdx.x * 64 + lane;
-    const int mode = min(m0, g.P - 1);
-    const int j = mode / nl;
-    const int l = mode - j * nl - kz;
+    int mode, j, l;
+    bool inside;  // the lane's mode exists (else it reads a valid one and idles)
+    if constexpr (PAIRED) {
+        const int groups = solve_pair_groups(kz);
+        if ((int)blockIdx.x >= g.nj * groups) return;  // past this instance's pairs (whole block)
+        j = (int)blockIdx.x / groups;
+        const int lq = ((int)blockIdx.x - j * groups) * 32 + (lane & 31);
+        const bool neg = lane >= 32;
+        inside = lq <= kz && !(neg && lq == 0);
+        const int lc = min(lq, kz);
+        l = neg ? -lc : lc;
+        mode = j * nl + kz + l;
+    } else {
+        if ((int)blockIdx.x * 64 >= g.P) return;  // past this instance's modes (whole block)
+        const int m0 = blockIdx.x * 64 + lane;
+        inside = m0 < g.P;
+        mode = min(m0, g.P - 1);
+        j = mode / nl;
+        l = mode - j * nl - kz;
+    }
     const int lp = l < 0 ? -l : l;
     const int pair = j * (kz + 1) + lp;
     const bool mean = (j == 0 && l == 0);
     // lanes past the last mode, and the -l columns of j = 0, only take part in
     // the barriers
-    const bool act = m0 < g.P && !(j == 0 && l < 0);
+    const bool act = inside && !(j == 0 && l < 0);
     const bool mirror = (j == 0 && l > 0);
     const int s0 = 1 + seg * L;
     const int len = max(0, min(s0 + L, nr - 1) - s0);
@@ -2026,8 +2050,6 @@ bool theta_fast(const Batch& B, hipStream_t s) {
     return false;
 }
 
-int solve_segment_rows(int nr);
-
 bool lane_length(int n) {
     switch (n) {
 #define TC_CASE(N) case N: return true;
@@ -2123,27 +2145,49 @@ void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, 
 
 // Segments of the segmented solve: 8 segments of L rows (L = 4 or 8), or 16
 // segments of 8 rows for up to 128 unknowns (at most 123 VGPRs per lane);
-// 0 above that (sequential kernel).  Returns 100 * segments + L.
-int solve_segment_rows(int nr) {
+// 0 above that (sequential kernel).  Code 100 * segments + L, plus
+// SOLVE_PAIRED for the paired lane layout, taken by default when the pairs
+// fill at least 85 % of the lanes (2 K_z + 1 modes per j over 64 lanes per
+// group of 32 pairs: K_z = 127 fills 255 of 256).
+constexpr int SOLVE_PAIRED = 10000;
+
+int solve_segment_rows(int nr, int kz) {
     const int nu = nr - 2;
-    if (nu <= 8 * 4) return 804;
-    if (nu <= 8 * 8) return 808;
-    if (nu <= 16 * 8) return 1608;
-    return 0;
+    int code = 0;
+    if (nu <= 8 * 4) code = 804;
+    else if (nu <= 8 * 8) code = 808;
+    else if (nu <= 16 * 8) code = 1608;
+    else return 0;
+    const int groups = (kz + 32) / 32;
+    if ((2.0 * kz + 1.0) >= 0.85 * 64.0 * groups) code += SOLVE_PAIRED;
+    return code;
 }
 
 bool solve_shape_fits(int code, int nr) {
-    if (code != 804 && code != 808 && code != 1608) return false;
-    return (code / 100) * (code % 100) >= nr - 2;
+    const int base = code % SOLVE_PAIRED;
+    if (code < 0 || code / SOLVE_PAIRED > 1) return false;
+    if (base != 804 && base != 808 && base != 1608) return false;
+    return (base / 100) * (base % 100) >= nr - 2;
 }
 
 void launch_solve(const Batch& B, int k, hipStream_t s) {
     // grid.y selects the equation, grid.z the instance
     const dim3 gseg((B.g.P + 63) / 64, 2, B.count);
+    // paired: B.g carries the largest nj and the largest K_z of the group
+    const dim3 gpair(B.g.nj * ((B.g.kz + 32) / 32), 2, B.count);
     switch (B.g.solve_seg) {
-        case 804: hipLaunchKernelGGL((k_solve_seg<4, 8>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
-        case 808: hipLaunchKernelGGL((k_solve_seg<8, 8>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
-        case 1608: hipLaunchKernelGGL((k_solve_seg<8, 16>), gseg, dim3(64 * 16), 0, s, B.inst, k); return;
+        case 804: hipLaunchKernelGGL((k_solve_seg<4, 8, false>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
+        case 808: hipLaunchKernelGGL((k_solve_seg<8, 8, false>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
+        case 1608: hipLaunchKernelGGL((k_solve_seg<8, 16, false>), gseg, dim3(64 * 16), 0, s, B.inst, k); return;
+        case SOLVE_PAIRED + 804:
+            hipLaunchKernelGGL((k_solve_seg<4, 8, true>), gpair, dim3(64 * 8), 0, s, B.inst, k);
+            return;
+        case SOLVE_PAIRED + 808:
+            hipLaunchKernelGGL((k_solve_seg<8, 8, true>), gpair, dim3(64 * 8), 0, s, B.inst, k);
+            return;
+        case SOLVE_PAIRED + 1608:
+            hipLaunchKernelGGL((k_solve_seg<8, 16, true>), gpair, dim3(64 * 16), 0, s, B.inst, k);
+            return;
     }
     dim3 grid((B.g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2, B.count);
     hipLaunchKernelGGL(k_solve_lu, grid, dim3(SOLVE_NT), 0, s, B.inst, k);

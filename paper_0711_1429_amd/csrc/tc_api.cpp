@@ -233,7 +233,7 @@ int alloc_instance(tc_ctx* c, Instance& in) {
     if ((rc = upload(c, in, &g.blu, s.blu))) return rc;
     if ((rc = upload(c, in, &g.dvh, s.dvh))) return rc;
     g.dv_seg = s.dv_seg;
-    g.solve_seg = solve_segment_rows(s.nr);
+    g.solve_seg = solve_segment_rows(s.nr, s.kz);
     g.dv_nseg = s.dv_nseg;
     if ((rc = upload(c, in, &g.m, s.m))) return rc;
     if ((rc = upload(c, in, &g.alpha, s.alpha))) return rc;
@@ -382,6 +382,7 @@ int build_classes(tc_ctx* c) {
             m.nj = std::max(m.nj, g.nj);
             m.P = std::max(m.P, g.P);
             m.npairs = std::max(m.npairs, g.npairs);
+            if (st == ST_SOLVE) m.kz = std::max(m.kz, g.kz);  // the paired grid covers every member
             m.rhs_rr = std::min(m.rhs_rr, g.rhs_rr);
             if (st == ST_THETA) m.nz = std::max(m.nz, g.nz);
             found->members.push_back(i);
@@ -999,7 +1000,7 @@ int tc_autotune(tc_ctx* c, int repeats) {
         if (rc || gr.g.solve_seg == 0) continue;
         int best_code = gr.g.solve_seg;
         double best = 1e30;
-        for (int code : {804, 808, 1608}) {
+        for (int code : {804, 808, 1608, 10804, 10808, 11608}) {
             if (!solve_shape_fits(code, gr.g.nr)) continue;
             gr.g.solve_seg = code;
             double ms = 0;
