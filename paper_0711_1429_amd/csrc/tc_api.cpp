@@ -1,6 +1,7 @@
 // C ABI of libtc.so (declared in include/tc.h): contexts, device memory,
 // field I/O with validation, the substep sequence and statistics.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -323,9 +324,15 @@ void group_stage(tc_ctx* c, int st, const LaunchGroup& gr, int k, hipStream_t s)
     }
 }
 
+// roctx range names of the substeps (a profiler shows each substep's
+// launches under its range; host-side markers, nothing is added to the stream)
+const char* const kSubstepRange[3] = {"tc substep 1", "tc substep 2", "tc substep 3"};
+
 int run_substep(tc_ctx* c, int k) {
+    roctxRangePushA(kSubstepRange[k]);
     for (int st = 0; st < ST_COUNT; ++st)
         for (auto& gr : c->groups[st]) group_stage(c, st, gr, k, c->stream);
+    roctxRangePop();
     return check_launch(c, "substep launch");
 }
 
@@ -715,7 +722,10 @@ int tc_step(tc_ctx* c, int nsteps) {
         if (int rc = capture_step(c)) return rc;
     for (int it = 0; it < nsteps; ++it) {
         if (graph) {
-            HIPCHK(c, hipGraphLaunch(c->step_graph, c->stream));
+            roctxRangePushA("tc step (graph replay)");
+            const hipError_t e = hipGraphLaunch(c->step_graph, c->stream);
+            roctxRangePop();
+            HIPCHK(c, e);
         } else {
             for (int k = 0; k < 3; ++k)
                 if (int rc = run_substep(c, k)) return rc;

@@ -37,8 +37,8 @@ def test_abi_host_code_under_sanitizers(tmp_path):
         subprocess.run([hipcc, "-O1", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-c",
                         os.path.join(CSRC, "kernels.hip"), "-o", kobj], check=True)
     exe = str(tmp_path / "abi_sanitize")
-    subprocess.run([gxx, *SAN, drv, *objs, kobj, "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib",
-                    "-o", exe], check=True)
+    subprocess.run([gxx, *SAN, drv, *objs, kobj, "-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx",
+                    "-Wl,-rpath,/opt/rocm/lib", "-o", exe], check=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
     out = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
     print(out.stdout[-3000:], out.stderr[-3000:])
