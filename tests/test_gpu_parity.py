@@ -451,6 +451,38 @@ def test_batched_instances_equal_single_runs():
     assert rel_l2(v, rv) < TOL and rel_l2(e, re_) < TOL
 
 
+def test_batched_workload_all_64_instances_equal_single_runs():
+    """The whole batched workload (64 instances of nine grid shapes, mixed
+    precision, as the benchmark runs it: launch parameters autotuned, steps
+    replayed from the captured graph) gives every instance bit for bit the
+    state it reaches alone in a context of its own with the same launch
+    parameters, after 5 steps."""
+    from paper_0711_1429_amd.synth import batched_instances
+    from tests.helpers import abi_geometry, fields_for
+    ws = batched_instances(64)
+    prec = tcb.TC_PREC_MIXED
+    multi = tcb.Solver([abi_geometry(w, prec) for w in ws])
+    fields = [fields_for(w, multi.grid(i)) for i, w in enumerate(ws)]
+    for i, f in enumerate(fields):
+        multi.load_fields(*f, inst=i)
+    multi.autotune(2)
+    multi.step(5)
+    for i, w in enumerate(ws):
+        one = tcb.Solver(abi_geometry(w, prec))
+        one.set_rhs_rows(multi.tuning(i)["rhs_rows"])
+        one.load_fields(*fields[i])
+        one.step(5)
+        got, want = multi.get_fields(i), one.get_fields()
+        same_shape = multi.tuning(i)["solve_shape"] == one.tuning()["solve_shape"]
+        for x, y, k in zip(got, want, ("v", "eta", "u_mean", "w_mean")):
+            if same_shape:
+                assert np.array_equal(x, y), (i, k)
+            else:  # the autotuner chose another segmentation of the same solve
+                assert rel_l2(np.atleast_1d(x), np.atleast_1d(y)) < 1e-12, (i, k)
+        one.close()
+    multi.close()
+
+
 def test_linear_flag_matches_oracle_without_products():
     """TC_FLAG_LINEAR: the step with the six products set to zero equals the
     oracle's step with its products replaced by zeros (a mixed instance set:
