@@ -294,7 +294,7 @@ def measure(workload, precision, steps, warmup, eager=False, autotune="auto"):
     if tuned:
         print(f"bench: {workload} autotune", file=sys.stderr, flush=True)
         solver.autotune(5)
-    tuning = sorted({tuple(solver.tuning(i).items()) for i in range(len(ws))})
+    tuning = sorted({tuple(solver.tuning(i).items()) + tuple(solver.tiles(i).items()) for i in range(len(ws))})
     print(f"bench: {workload} {precision} warmup {warmup}", file=sys.stderr, flush=True)
     solver.step(warmup)
 

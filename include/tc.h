@@ -216,10 +216,12 @@ int tc_stats_noalloc(tc_ctx* ctx, int inst, tc_stats_t* out);
 /* Pick, by timing on the device, the launch parameters that do not change the
  * method: the rows per chunk of the explicit-term kernel (the columns split
  * into 1, 2, 3, 4, 5, 6, 8 or 10 chunks, each instance's rows divided evenly,
- * or 21, 16, 11 or 6 rows for every instance) and the segment shape of the
+ * or 21, 16, 11 or 6 rows for every instance), the segment shape of the
  * radial solve (8 x 4, 8 x 8 or 16 x 8 rows, each with one lane per mode or
  * with the two signs of l of a wavenumber pair in the two halves of a
- * wavefront), per launch group.  Runs one substep to fill the intermediates, times `repeats`
+ * wavefront) and the tile shapes of the fixed-length transform kernels (z
+ * kernels at half, the default or twice the columns per block; theta kernel
+ * at 1, 2 or 4 wavefronts per block; see tc_tiles), per launch group.  Runs one substep to fill the intermediates, times `repeats`
  * launches (1..1000) of each candidate and restores the state, the N
  * registers and the time exactly, so the fields are unchanged on return.
  * Allocates a temporary copy of the state (freed before returning).  The
@@ -241,6 +243,28 @@ int tc_set_rhs_rows(tc_ctx* ctx, int inst, int rows);
  * when the two signs of l of a pair share a wavefront (0: one lane walks
  * every row).  Either pointer may be NULL. */
 int tc_tuning(const tc_ctx* ctx, int inst, int* rhs_rows, int* solve_shape);
+
+/* Set the segment shape of the radial solve (a code as tc_tuning reports:
+ * 804, 808 or 1608, plus 10000 for the paired lane layout) for every instance
+ * that shares instance `inst`'s solve launch.  TC_EINVAL if the shape does not
+ * cover one of them or the solve is not segmented.  The two layouts and the
+ * segmentations solve the same systems (results equal to rounding).  The step
+ * graph is recaptured on the next tc_step. */
+int tc_set_solve_shape(tc_ctx* ctx, int inst, int code);
+
+/* Set the tile shapes of the transform stages (codes as tc_tiles reports)
+ * for every instance that shares instance `inst`'s launch of each stage.
+ * TC_EINVAL if a shape is not compiled for the stage's transform length and
+ * precision.  Results are bit-identical for every tile shape.  The step graph
+ * is recaptured on the next tc_step. */
+int tc_set_tiles(tc_ctx* ctx, int inst, int zinv, int theta, int zfwd);
+
+/* The tile shapes of the transform stages in use for instance `inst` (after
+ * tc_create: 0 everywhere, the defaults; after tc_autotune: the choice of the
+ * instance's launch group).  z kernels (inverse and forward): 0 the default
+ * columns per block, 1 half of them, 2 twice; theta kernel: 0 the default
+ * wavefronts per block, 1, 2 or 3 for 1, 2 or 4.  Any pointer may be NULL. */
+int tc_tiles(const tc_ctx* ctx, int inst, int* zinv, int* theta, int* zfwd);
 
 /* Per-kernel timing with HIP events on the context's stream.
  * enable = 1 starts recording (and clears the totals), 0 stops.  While on,

@@ -22,6 +22,8 @@ Readings taken where the paper is silent or ambiguous:
 
 from dataclasses import dataclass, field
 
+import math
+
 import numpy as np
 
 
@@ -93,7 +95,12 @@ class Discretisation:
         n = np.arange(g.nr, dtype=np.float64)
         xi = -1.0 + 2.0 * n / (g.nr - 1)
         if g.stretch > 0:
-            t = np.tanh(g.stretch * xi) / np.tanh(g.stretch)
+            # the C library's tanh point by point (numpy's vectorised tanh
+            # can be one unit in the last place off, and the compact
+            # coefficients of the clustered near-wall rows amplify a
+            # one-ulp move of a grid point about a thousandfold)
+            ts = math.tanh(g.stretch)
+            t = np.array([math.tanh(g.stretch * x) for x in xi]) / ts
         else:
             t = xi
         self.r = self.ri + d * (1.0 + t) / 2.0

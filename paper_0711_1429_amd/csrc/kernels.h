@@ -99,6 +99,9 @@ struct DevGeom {
     const double* wr;       // [nr] trapezoid weight * r
     FftPlanDev plan_theta, plan_z;
     int generic_fft;        // 1: run-time-length FFT kernels even for compiled lengths
+    int tile_zinv;          // tile shape of the fixed-length z kernels: 0 default columns per
+    int tile_zfwd;          //   block, 1 half, 2 twice (when that shape is compiled)
+    int tile_theta;         // theta kernel wavefronts per block: 0 default, 1, 2, 3 for 1, 2, 4
     int linear;             // 1: no products (the transform stages are not launched)
 };
 
@@ -185,6 +188,9 @@ int rhs_rows(int nr, int P, long long waves_per_chunk_row, bool fp32);
 // shape `code` is compiled and covers nr - 2 unknowns
 int solve_segment_rows(int nr, int kz);
 bool solve_shape_fits(int code, int nr);
+// whether tile code `code` of a transform stage (ST_ZINV, ST_THETA, ST_ZFWD)
+// is compiled for the group's transform length and precision
+bool tile_variant_ok(int stage, const DevGeom& g, bool fp32, int code);
 // precomputed LU factors of substep k (run once per context and k)
 void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, hipStream_t s);
 void launch_solve(const Batch& B, int k, hipStream_t s);

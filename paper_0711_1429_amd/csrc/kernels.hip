@@ -1590,9 +1590,26 @@ constexpr int zlane_cols(int N, int esize) {
 // element per column for consecutive columns, so the pitch is offset from N
 // by 16 / JB elements, which puts the JB columns of a group of 16 lanes in
 // distinct element slots (and so spreads them over the banks).
-constexpr int zlane_pitch(int N, int esize) {
-    const int jb = zlane_cols(N, esize);
-    return N + ((16 % jb) == 0 ? 16 / jb : 1);
+constexpr int zlane_pitch_jb(int N, int jb) { return N + ((16 % jb) == 0 ? 16 / jb : 1); }
+constexpr int zlane_pitch(int N, int esize) { return zlane_pitch_jb(N, zlane_cols(N, esize)); }
+
+// Tile-shape variants the autotuner may pick for a launch group: the z
+// kernels at half or twice the default columns per block (at most 32
+// columns, 1024 threads and 160 KB of LDS per block), the theta kernel at 1,
+// 2 or 4 wavefronts per block.  Code 0 is the default shape.
+constexpr int zlane_variant_cols(int N, int esize, int code) {
+    const int d = zlane_cols(N, esize);
+    const int jb = code == 1 ? d / 2 : (code == 2 ? d * 2 : d);
+    return jb < 1 ? 1 : jb;
+}
+template <typename T, int N>
+constexpr bool zlane_variant_ok(int code) {
+    if (code < 0 || code > 2) return false;
+    const int jb = zlane_variant_cols(N, (int)sizeof(C<T>), code);
+    if (code == 1 && zlane_cols(N, (int)sizeof(C<T>)) < 2) return false;
+    return jb <= 32 && jb * lane::Plan<N>::TL <= 1024 &&
+           (long long)jb * zlane_pitch_jb(N, jb) * (long long)sizeof(C<T>) + (lane::tw_size<N>() + 1) * (long long)sizeof(C<T>) <=
+               160 * 1024;
 }
 
 // The value v of lane src of this wavefront (ds_bpermute: the LDS crossbar,
@@ -1654,8 +1671,8 @@ constexpr int theta_waves() { return sizeof(T) == 8 ? 1 : 2; }
 // three), forms each of the six products pointwise in registers and
 // forward-transforms it through its own LDS region.  The wavefronts of a
 // block share only the twiddle table, so no block-wide barrier follows it.
-template <typename T, int N>
-__global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_per_eu(2))) void k_theta_wave(
+template <typename T, int N, int WV>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) void k_theta_wave(
     const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
@@ -1663,19 +1680,19 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
     auto* __restrict__ pb = glb((C<T>*)b.pb);
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
-    __shared__ C<T> lds[theta_waves<T>() * W * N];
+    __shared__ C<T> lds[WV * W * N];
     __shared__ C<T> twl[lane::tw_size<N>() + 1];  // per-pass twiddles
-    if ((int)blockIdx.y >= g.nr || (int)blockIdx.x * theta_waves<T>() * W >= g.nz / 2) return;  // whole block
+    if ((int)blockIdx.y >= g.nr || (int)blockIdx.x * WV * W >= g.nz / 2) return;  // whole block
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lw = threadIdx.x & 63;
     const int grp = lw / TL;
     const int gl = lw - grp * TL;
-    const int rp = (blockIdx.x * theta_waves<T>() + wv) * W + grp;
+    const int rp = (blockIdx.x * WV + wv) * W + grp;
     const int nz = g.nz, nr = g.nr;
     const bool active = rp < nz / 2;
     const int r = blockIdx.y;
     const int z0 = 2 * rp;
-    lane::fill_twiddles<T, N>(twl, glb(tw_t<T>(g)), threadIdx.x, 64 * theta_waves<T>());
+    lane::fill_twiddles<T, N>(twl, glb(tw_t<T>(g)), threadIdx.x, 64 * WV);
     // the z-spectral rows of field fl packed into the complex sequence of the
     // two real rows (z0, z0 + 1).  K_theta = (N - 1) / 3 is fixed by N, so
     // which of the kept band, the zero band and the mirrored band a register
@@ -1762,8 +1779,8 @@ __global__ __launch_bounds__(64 * theta_waves<T>()) __attribute__((amdgpu_waves_
 
 // inverse z transform of u, v, w for JB j-columns of one plane; v, eta and
 // D v are read once per element.
-template <typename T, int N>
-__global__ __launch_bounds__(zlane_cols(N, sizeof(C<T>)) * lane::Plan<N>::TL) void k_zinv_lane(const InstDev* __restrict__ I) {
+template <typename T, int N, int JBV>
+__global__ __launch_bounds__(JBV * lane::Plan<N>::TL) void k_zinv_lane(const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
     const auto* __restrict__ v = glb(b.v);
@@ -1773,7 +1790,7 @@ __global__ __launch_bounds__(zlane_cols(N, sizeof(C<T>)) * lane::Plan<N>::TL) vo
     const auto* __restrict__ wmean = glb(b.wmean);
     auto* __restrict__ zb = glb((C<T>*)b.zb);
     using PL = lane::Plan<N>;
-    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N, sizeof(C<T>)), NTH = JB * TL, PITCH = zlane_pitch(N, sizeof(C<T>));
+    constexpr int TL = PL::TL, P = PL::P, JB = JBV, NTH = JB * TL, PITCH = zlane_pitch_jb(N, JB);
     __shared__ C<T> lds[JB * PITCH];
     const int c = threadIdx.x / TL;
     const int gl = threadIdx.x - c * TL;
@@ -1864,14 +1881,14 @@ __global__ __launch_bounds__(zlane_cols(N, sizeof(C<T>)) * lane::Plan<N>::TL) vo
 
 // forward z transform of the six products for JB j-columns of one plane,
 // truncation to |l| <= K_z and normalisation.
-template <typename T, int N>
-__global__ __launch_bounds__(zlane_cols(N, sizeof(C<T>)) * lane::Plan<N>::TL) void k_zfwd_lane(const InstDev* __restrict__ I) {
+template <typename T, int N, int JBV>
+__global__ __launch_bounds__(JBV * lane::Plan<N>::TL) void k_zfwd_lane(const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
     const auto* __restrict__ pb = glb((const C<T>*)b.pb);
     auto* __restrict__ ps = glb((C<T>*)b.ps);
     using PL = lane::Plan<N>;
-    constexpr int TL = PL::TL, P = PL::P, JB = zlane_cols(N, sizeof(C<T>)), NTH = JB * TL, PITCH = zlane_pitch(N, sizeof(C<T>));
+    constexpr int TL = PL::TL, P = PL::P, JB = JBV, NTH = JB * TL, PITCH = zlane_pitch_jb(N, JB);
     __shared__ C<T> lds[JB * PITCH];
     const int c = threadIdx.x / TL;
     const int gl = threadIdx.x - c * TL;
@@ -1998,23 +2015,52 @@ void launch_dv(const Batch& B, hipStream_t s) {
 
 #define TC_LANE_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768)
 
+template <typename T, int N, int CODE>
+void zinv_lane_v(const Batch& B, hipStream_t s) {
+    if constexpr (zlane_variant_ok<T, N>(CODE)) {
+        constexpr int JB = zlane_variant_cols(N, sizeof(C<T>), CODE);
+        dim3 grid((B.g.nj + JB - 1) / JB, B.g.nr, B.count);
+        hipLaunchKernelGGL((k_zinv_lane<T, N, JB>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, B.inst);
+    }
+}
 template <typename T, int N>
 void zinv_lane(const Batch& B, hipStream_t s) {
-    constexpr int JB = zlane_cols(N, sizeof(C<T>));
-    dim3 grid((B.g.nj + JB - 1) / JB, B.g.nr, B.count);
-    hipLaunchKernelGGL((k_zinv_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, B.inst);
+    const int code = zlane_variant_ok<T, N>(B.g.tile_zinv) ? B.g.tile_zinv : 0;
+    if (code == 1) zinv_lane_v<T, N, 1>(B, s);
+    else if (code == 2) zinv_lane_v<T, N, 2>(B, s);
+    else zinv_lane_v<T, N, 0>(B, s);
+}
+template <typename T, int N, int CODE>
+void zfwd_lane_v(const Batch& B, hipStream_t s) {
+    if constexpr (zlane_variant_ok<T, N>(CODE)) {
+        constexpr int JB = zlane_variant_cols(N, sizeof(C<T>), CODE);
+        dim3 grid((B.g.nj + JB - 1) / JB, B.g.nr, B.count);
+        hipLaunchKernelGGL((k_zfwd_lane<T, N, JB>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, B.inst);
+    }
 }
 template <typename T, int N>
 void zfwd_lane(const Batch& B, hipStream_t s) {
-    constexpr int JB = zlane_cols(N, sizeof(C<T>));
-    dim3 grid((B.g.nj + JB - 1) / JB, B.g.nr, B.count);
-    hipLaunchKernelGGL((k_zfwd_lane<T, N>), grid, dim3(JB * lane::Plan<N>::TL), 0, s, B.inst);
+    const int code = zlane_variant_ok<T, N>(B.g.tile_zfwd) ? B.g.tile_zfwd : 0;
+    if (code == 1) zfwd_lane_v<T, N, 1>(B, s);
+    else if (code == 2) zfwd_lane_v<T, N, 2>(B, s);
+    else zfwd_lane_v<T, N, 0>(B, s);
 }
+template <typename T, int N, int WV>
+void theta_lane_v(const Batch& B, hipStream_t s) {
+    constexpr int RB = (64 / lane::Plan<N>::TL) * WV;  // row pairs per block
+    dim3 grid((B.g.nz / 2 + RB - 1) / RB, B.g.nr, B.count);
+    hipLaunchKernelGGL((k_theta_wave<T, N, WV>), grid, dim3(64 * WV), 0, s, B.inst);
+}
+// theta tile code: 0 the default wavefronts per block (theta_waves), 1, 2 or
+// 4 explicitly (codes 1, 2, 3)
 template <typename T, int N>
 void theta_lane(const Batch& B, hipStream_t s) {
-    constexpr int RB = (64 / lane::Plan<N>::TL) * theta_waves<T>();  // row pairs per block
-    dim3 grid((B.g.nz / 2 + RB - 1) / RB, B.g.nr, B.count);
-    hipLaunchKernelGGL((k_theta_wave<T, N>), grid, dim3(64 * theta_waves<T>()), 0, s, B.inst);
+    switch (B.g.tile_theta) {
+        case 1: theta_lane_v<T, N, 1>(B, s); return;
+        case 2: theta_lane_v<T, N, 2>(B, s); return;
+        case 3: theta_lane_v<T, N, 4>(B, s); return;
+    }
+    theta_lane_v<T, N, theta_waves<T>()>(B, s);
 }
 
 template <typename T>
@@ -2055,6 +2101,30 @@ bool lane_length(int n) {
 #define TC_CASE(N) case N: return true;
         TC_LANE_SIZES(TC_CASE)
 #undef TC_CASE
+    }
+    return false;
+}
+
+template <typename T>
+bool tile_ok_t(int stage, int n, int code) {
+    if (stage == ST_THETA) return code >= 0 && code <= 3 && lane_length(n);
+    switch (n) {
+#define TC_CASE(N) case N: return zlane_variant_ok<T, N>(code);
+        TC_LANE_SIZES(TC_CASE)
+#undef TC_CASE
+    }
+    return false;
+}
+
+bool tile_variant_ok(int stage, const DevGeom& g, bool fp32, int code) {
+    if (g.generic_fft) return code == 0;
+    if (stage == ST_ZINV || stage == ST_ZFWD) {
+        if (!lane_length(g.nz) || g.kz != (g.nz - 1) / 3) return code == 0;
+        return fp32 ? tile_ok_t<float>(stage, g.nz, code) : tile_ok_t<double>(stage, g.nz, code);
+    }
+    if (stage == ST_THETA) {
+        if (!lane_length(g.ntheta) || g.kt != (g.ntheta - 1) / 3) return code == 0;
+        return fp32 ? tile_ok_t<float>(stage, g.ntheta, code) : tile_ok_t<double>(stage, g.ntheta, code);
     }
     return false;
 }
@@ -2146,21 +2216,19 @@ void launch_factor(const DevGeom& g, const DevBuf& b, const StepCoef& c, int k, 
 // Segments of the segmented solve: 8 segments of L rows (L = 4 or 8), or 16
 // segments of 8 rows for up to 128 unknowns (at most 123 VGPRs per lane);
 // 0 above that (sequential kernel).  Code 100 * segments + L, plus
-// SOLVE_PAIRED for the paired lane layout, taken by default when the pairs
-// fill at least 85 % of the lanes (2 K_z + 1 modes per j over 64 lanes per
-// group of 32 pairs: K_z = 127 fills 255 of 256).
+// SOLVE_PAIRED for the paired lane layout.  The default is one lane per mode:
+// on 129 x 65280 modes the paired layout reads half the factor bytes but
+// measured 2 % slower (the second read of a pair's factors comes from cache);
+// the autotuner has both.
 constexpr int SOLVE_PAIRED = 10000;
 
 int solve_segment_rows(int nr, int kz) {
+    (void)kz;
     const int nu = nr - 2;
-    int code = 0;
-    if (nu <= 8 * 4) code = 804;
-    else if (nu <= 8 * 8) code = 808;
-    else if (nu <= 16 * 8) code = 1608;
-    else return 0;
-    const int groups = (kz + 32) / 32;
-    if ((2.0 * kz + 1.0) >= 0.85 * 64.0 * groups) code += SOLVE_PAIRED;
-    return code;
+    if (nu <= 8 * 4) return 804;
+    if (nu <= 8 * 8) return 808;
+    if (nu <= 16 * 8) return 1608;
+    return 0;
 }
 
 bool solve_shape_fits(int code, int nr) {

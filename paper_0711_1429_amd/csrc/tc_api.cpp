@@ -901,8 +901,13 @@ int time_stage(tc_ctx* c, int st, const LaunchGroup& gr, int k, int reps, hipEve
                double* ms) {
     const Batch B = batch_of(gr);
     auto launch = [&] {
-        if (st == ST_RHS) launch_rhs(B, c->fp32, step_coef(k), k, c->stream);
-        else launch_solve(B, k, c->stream);
+        switch (st) {
+            case ST_RHS: launch_rhs(B, c->fp32, step_coef(k), k, c->stream); break;
+            case ST_SOLVE: launch_solve(B, k, c->stream); break;
+            case ST_ZINV: launch_zinv(B, c->fp32, c->stream); break;
+            case ST_THETA: launch_theta(B, c->fp32, c->stream); break;
+            case ST_ZFWD: launch_zfwd(B, c->fp32, c->stream); break;
+        }
     };
     launch();  // warm
     HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -1023,6 +1028,32 @@ int tc_autotune(tc_ctx* c, int repeats) {
         gr.g.solve_seg = best_code;
         for (int i : gr.members) c->inst[i].g.solve_seg = best_code;
     }
+    // tile shapes of the transform stages, per launch group (the stages read
+    // only the state and the previous stage's output, so they can be
+    // relaunched at will; the arithmetic of every element is the same)
+    for (int st : {ST_ZINV, ST_THETA, ST_ZFWD}) {
+        for (auto& gr : c->groups[st]) {
+            if (rc) break;
+            int& field = st == ST_ZINV ? gr.g.tile_zinv : (st == ST_THETA ? gr.g.tile_theta : gr.g.tile_zfwd);
+            int best_code = field;
+            double best = 1e30;
+            for (int code = 0; code <= 3; ++code) {
+                if (!tile_variant_ok(st, gr.g, c->fp32, code)) continue;
+                field = code;
+                double ms = 0;
+                if ((rc = time_stage(c, st, gr, k, repeats, e0, e1, &ms))) break;
+                if (ms < best) {
+                    best = ms;
+                    best_code = code;
+                }
+            }
+            field = best_code;
+            for (int i : gr.members) {
+                DevGeom& mg = c->inst[i].g;
+                (st == ST_ZINV ? mg.tile_zinv : (st == ST_THETA ? mg.tile_theta : mg.tile_zfwd)) = best_code;
+            }
+        }
+    }
     if (!rc) rc = upload_descriptors(c);
     // restore the state
     for (auto& cp : saved)
@@ -1062,6 +1093,69 @@ int tc_tuning(const tc_ctx* cc, int inst, int* rhs_rows_out, int* solve_shape_ou
     if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
     if (rhs_rows_out) *rhs_rows_out = in->g.rhs_rr;
     if (solve_shape_out) *solve_shape_out = in->g.solve_seg;
+    return TC_OK;
+}
+
+namespace {
+
+// The launch group of stage st that holds instance inst.
+LaunchGroup* group_of(tc_ctx* c, int st, int inst) {
+    for (auto& gr : c->groups[st])
+        for (int i : gr.members)
+            if (i == inst) return &gr;
+    return nullptr;
+}
+
+}  // namespace
+
+int tc_set_solve_shape(tc_ctx* c, int inst, int code) {
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    LaunchGroup* gr = group_of(c, ST_SOLVE, inst);
+    if (!gr || gr->g.solve_seg == 0) return fail(c, TC_EINVAL, "this instance's solve is not segmented");
+    for (int i : gr->members)
+        if (!solve_shape_fits(code, c->inst[i].g.nr))
+            return fail(c, TC_EINVAL, "solve shape " + std::to_string(code) + " does not fit instance " +
+                                          std::to_string(i));
+    gr->g.solve_seg = code;
+    for (int i : gr->members) c->inst[i].g.solve_seg = code;
+    drop_graph(c);
+    return upload_descriptors(c);
+}
+
+int tc_set_tiles(tc_ctx* c, int inst, int zinv, int theta, int zfwd) {
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    const int want[3] = {zinv, theta, zfwd};
+    const int stages[3] = {ST_ZINV, ST_THETA, ST_ZFWD};
+    for (int q = 0; q < 3; ++q) {
+        LaunchGroup* gr = group_of(c, stages[q], inst);
+        if (gr && !tile_variant_ok(stages[q], gr->g, c->fp32, want[q]))
+            return fail(c, TC_EINVAL, "tile code " + std::to_string(want[q]) + " is not compiled for this stage");
+        if (!gr && want[q] != 0) return fail(c, TC_EINVAL, "this instance has no transform stages");
+    }
+    for (int q = 0; q < 3; ++q) {
+        LaunchGroup* gr = group_of(c, stages[q], inst);
+        if (!gr) continue;
+        auto field = [&](DevGeom& g) -> int& {
+            return q == 0 ? g.tile_zinv : (q == 1 ? g.tile_theta : g.tile_zfwd);
+        };
+        field(gr->g) = want[q];
+        for (int i : gr->members) field(c->inst[i].g) = want[q];
+    }
+    drop_graph(c);
+    return upload_descriptors(c);
+}
+
+int tc_tiles(const tc_ctx* cc, int inst, int* zinv, int* theta, int* zfwd) {
+    tc_ctx* c = const_cast<tc_ctx*>(cc);
+    Instance* in = get_inst(c, inst);
+    if (!in) return c ? fail(c, TC_EINVAL, "bad instance index") : TC_EINVAL;
+    if (zinv) *zinv = in->g.tile_zinv;
+    if (theta) *theta = in->g.tile_theta;
+    if (zfwd) *zfwd = in->g.tile_zfwd;
     return TC_OK;
 }
 

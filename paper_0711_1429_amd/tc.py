@@ -83,6 +83,10 @@ _SIGNATURES = {
     "tc_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "tc_set_solve_shape": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "tc_set_tiles": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "tc_tiles": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]),
     "tc_kernel_times": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
     "tc_kernel_count": (ctypes.c_int, []),
     "tc_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -248,6 +252,17 @@ class Solver:
         rr, sh = ctypes.c_int(), ctypes.c_int()
         self._check(self.lib.tc_tuning(self.ctx, inst, ctypes.byref(rr), ctypes.byref(sh)))
         return {"rhs_rows": rr.value, "solve_shape": sh.value}
+
+    def set_solve_shape(self, code, inst=0):
+        self._check(self.lib.tc_set_solve_shape(self.ctx, inst, int(code)))
+
+    def set_tiles(self, zinv=0, theta=0, zfwd=0, inst=0):
+        self._check(self.lib.tc_set_tiles(self.ctx, inst, int(zinv), int(theta), int(zfwd)))
+
+    def tiles(self, inst=0):
+        zi, th, zf = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.tc_tiles(self.ctx, inst, ctypes.byref(zi), ctypes.byref(th), ctypes.byref(zf)))
+        return {"zinv": zi.value, "theta": th.value, "zfwd": zf.value}
 
     def timing(self, enable):
         self._check(self.lib.tc_timing(self.ctx, int(bool(enable))))

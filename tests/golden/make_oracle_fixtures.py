@@ -1,6 +1,6 @@
 """Write the oracle fixtures the GPU parity tests compare against.
 
-    python tests/golden/make_oracle_fixtures.py WORKLOAD STEP [STEP ...]
+    python tests/golden/make_oracle_fixtures.py [--workers W] WORKLOAD STEP [STEP ...]
 
 Runs the FP64 oracle (``oracle/``) from the seeded initial fields of
 ``paper_0711_1429_amd.synth`` and, after each listed number of whole RK3
@@ -19,6 +19,13 @@ low-wavenumber systems whose mass operator carries the large 1/k^2, Appendix
 eq. (final-v)), the modes of largest |alpha| and largest m, and 40 other modes
 drawn with numpy's default_rng(11).  Nothing here reads the HIP library: only
 the oracle and the seeded input generator are called.
+
+With --workers W > 1 each substep runs the oracle's own functions on parts
+of the grid in W forked processes: the velocity recovery and the explicit
+terms and banded solves split by modes, the dealiased products by radial
+planes (every mode's solves and every plane's transforms are independent),
+the mean flow in the parent, in the order of ``Oracle.substep``; the result
+is the serial one bit for bit (checked by --check-serial on the first step).
 """
 
 import os
@@ -52,11 +59,99 @@ def sample_modes(nj, nl):
     return np.unique(np.concatenate([low, high, extra]).astype(np.int64))
 
 
+def parallel_substep(orc, k, workers):
+    """Oracle.substep(k) with its independent work split over forked
+    processes (see the module docstring)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+
+    from oracle import equations as oeq
+    from oracle.spectral import products as oracle_products
+
+    nr, M = orc.v.shape
+    nj, nl = orc.disc.nj, orc.disc.nl
+    keys = ("uu", "uv", "uw", "vv", "vw", "ww")
+    shm = shared_memory.SharedMemory(create=True, size=13 * nr * M * 16)
+    ctx = mp.get_context("fork")
+
+    def run(target, parts):
+        def one(*a):
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                target(*a)
+        procs = [ctx.Process(target=one, args=a) for a in parts]
+        for p in procs:
+            p.start()
+        for p in procs:
+            p.join()
+        if any(p.exitcode != 0 for p in procs):
+            raise RuntimeError("a worker failed")
+
+    try:
+        A = np.ndarray((13, nr, M), dtype=np.complex128, buffer=shm.buf)
+        U, W, Cc, P, NV, NE, VN, EN = A[0], A[1], A[2], A[3:9], A[9], A[10], A[11], A[12]
+
+        def recover(sub):
+            dv = orc.ops.radial_derivative(orc.v[:, sub])
+            u, w, c = oeq.recover_velocity(orc.ops, orc._sub_mc(sub), orc.v[:, sub], orc.eta[:, sub], dv)
+            U[:, sub], W[:, sub], Cc[:, sub] = u, w, c
+
+        run(recover, [(part,) for part in np.array_split(np.arange(M), workers)])
+        U[:, orc.mean_index] = orc.u_mean
+        W[:, orc.mean_index] = orc.w_mean
+
+        def planes(r0, r1):
+            sh = (r1 - r0, nj, nl)
+            out = oracle_products(U[r0:r1].reshape(sh), orc.v[r0:r1].reshape(sh), W[r0:r1].reshape(sh),
+                                  orc.geo.ntheta, orc.geo.nz)
+            for q, key in enumerate(keys):
+                P[q, r0:r1] = out[key].reshape(r1 - r0, -1)
+
+        bounds = np.linspace(0, nr, workers + 1).astype(int)
+        run(planes, [(int(bounds[i]), int(bounds[i + 1])) for i in range(workers)])
+        prods = {key: P[q] for q, key in enumerate(keys)}
+        idx = np.flatnonzero(~orc.mc.is_mean)
+
+        def radial(sub):
+            nv, ne = orc.explicit_terms(sub, U, orc.v, W, Cc, prods)
+            vn, en = orc.radial_update(k, sub, orc.v, orc.eta, nv, ne, orc.nv_prev[:, sub], orc.neta_prev[:, sub])
+            NV[:, sub], NE[:, sub], VN[:, sub], EN[:, sub] = nv, ne, vn, en
+
+        run(radial, [(part,) for part in np.array_split(idx, workers)])
+        um, wm, n_u, n_w = orc.mean_update(k, prods, orc.u_mean, orc.w_mean, orc.nu_prev, orc.nw_prev)
+        orc.v[:, idx] = VN[:, idx]
+        orc.eta[:, idx] = EN[:, idx]
+        orc.nv_prev[:, idx] = NV[:, idx]
+        orc.neta_prev[:, idx] = NE[:, idx]
+        orc.u_mean, orc.w_mean = um, wm
+        orc.nu_prev, orc.nw_prev = n_u, n_w
+    finally:
+        shm.close()
+        shm.unlink()
+
+
+def parallel_step(orc, workers):
+    for k in range(3):
+        parallel_substep(orc, k, workers)
+    orc.time += orc.geo.dt
+    orc.steps += 1
+
+
 def fixture_path(workload, steps):
     return os.path.join(HERE, f"oracle_{workload}_step{steps}.npz")
 
 
 def main(argv):
+    workers, check = 1, False
+    while argv and argv[0].startswith("--"):
+        if argv[0] == "--workers":
+            workers = int(argv[1])
+            argv = argv[2:]
+        elif argv[0] == "--check-serial":
+            check = True
+            argv = argv[1:]
+        else:
+            raise SystemExit(f"unknown option {argv[0]}")
     name = argv[0]
     checkpoints = sorted(int(x) for x in argv[1:])
     w = WORKLOADS[name]
@@ -67,9 +162,22 @@ def main(argv):
     nj, nl = orc.disc.nj, orc.disc.nl
     modes = sample_modes(nj, nl)
     t0 = time.time()
+    if check and workers > 1:
+        ref = Oracle(geo)
+        ref.load(*initial_fields(ref.disc.r, w["zeta"], w["ntheta"], w["nz"], w["amplitude"], w["seed"]))
+        ref.step(1)
+        parallel_step(orc, workers)
+        same = all(np.array_equal(a, b) for a, b in zip(orc.fields(), ref.fields()))
+        print(f"{name}: first step on {workers} processes equals the serial oracle bit for bit: {same}", flush=True)
+        if not same:
+            raise SystemExit(1)
+        del ref
     for target in checkpoints:
         while orc.steps < target:
-            orc.step(1)
+            if workers > 1:
+                parallel_step(orc, workers)
+            else:
+                orc.step(1)
             print(f"{name}: step {orc.steps} ({time.time() - t0:.0f} s)", flush=True)
         dv, u, ww, c = orc.velocity()
         s = orc.stats()

@@ -126,6 +126,10 @@ int main() {
         CHECK(tc_timing(c, 1) == TC_EINVAL);
         CHECK(tc_autotune(c, 1) == TC_EINVAL);
         CHECK(tc_set_stream(c, nullptr) == TC_EINVAL);
+        CHECK(tc_set_solve_shape(c, 0, 804) == TC_EINVAL);
+        CHECK(tc_set_tiles(c, 0, 0, 0, 0) == TC_EINVAL);
+        int zi = -1, th = -1, zf = -1;
+        CHECK(tc_tiles(c, 0, &zi, &th, &zf) == TC_OK && zi == 0 && th == 0 && zf == 0);
         CHECK(tc_destroy(c) == TC_OK);
         std::printf("dry-run context nr=%d ntheta=%d nz=%d ok\n", g.nr, g.ntheta, g.nz);
     }

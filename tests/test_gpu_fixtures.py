@@ -63,7 +63,26 @@ def fp64_tol(n):
     return 1e-12 * max(1.0, n / 10.0)
 
 
-def compare_with_fixture(gpu, fx, tol, tol_torque, label, strict_means=True):
+def torque_condition(name, w_mean):
+    """Condition numbers of the wall shear g = |D w - w / r| at the inner and
+    outer wall (eq. (torque)): sum |terms| / |g|, with D w from the one-sided
+    compact row at the wall (the oracle's coefficients).  On a clustered grid
+    the inner-wall row's large coefficients cancel to a small g, so the
+    rounding of the mean profile (both sides agree to ~1e-15 there) is
+    amplified by this factor in the torque."""
+    from oracle import Oracle
+    from tests.helpers import oracle_geometry
+    o = Oracle(oracle_geometry(workload(name)))
+    d1, r = o.coef["d1"], o.disc.r
+    out = []
+    for row, pts in ((d1[0], slice(0, 5)), (d1[-1], slice(len(r) - 5, len(r)))):
+        wall = 0 if pts.start == 0 else len(r) - 1
+        terms = np.concatenate([row * w_mean[pts], [w_mean[wall] / r[wall]]])
+        out.append(float(np.sum(np.abs(terms)) / abs(terms[:-1].sum() - terms[-1])))
+    return out
+
+
+def compare_with_fixture(gpu, fx, tol, tol_torque, label, strict_means=True, kappa=None, steps=1):
     """Relative L2 differences on the sampled modes, Hermitian weights c_0 = 1,
     c_j = 2: v, eta, w' (the sampled w, no mean), and u and w with their mean
     profiles (the (0,0) mode) included.  With strict_means the mean profiles
@@ -107,9 +126,18 @@ def compare_with_fixture(gpu, fx, tol, tol_torque, label, strict_means=True):
         if not means["u_mean"] <= 10 * tol:
             bad["u_mean"] = means["u_mean"]
     assert not bad, (label, bad)
-    for k in ("torque_in", "torque_out"):
-        assert serr[k] <= tol_torque, (label, k, serr[k])
-    for k in ("retau_in", "retau_out", "energy", "energy_pert"):
+    for q, k in enumerate(("torque_in", "torque_out")):
+        # in FP64 the torque may carry the mean profile's rounding times the
+        # wall row's cancellation (ten times the unit roundoff of each term,
+        # growing over a run like the fields' bar)
+        grow = max(1.0, steps / 10.0)
+        bound = max(tol_torque, 10 * 2.2e-16 * kappa[q] * grow) if kappa else tol_torque
+        assert serr[k] <= bound, (label, k, serr[k], bound)
+    for q, k in enumerate(("retau_in", "retau_out")):  # Re_tau ~ sqrt(g): half the torque's relative error
+        bound = (max(tol, tol_torque, 10 * 2.2e-16 * kappa[q] * max(1.0, steps / 10.0) / 2) if kappa
+                 else max(tol, tol_torque))
+        assert serr[k] <= bound, (label, k, serr[k], bound)
+    for k in ("energy", "energy_pert"):
         assert serr[k] <= max(tol, tol_torque), (label, k, serr[k])
     return errs
 
@@ -131,7 +159,10 @@ def test_fp64_matches_oracle_checkpoints(name, flags):
     for n in cps:
         g.step(n - done)
         done = n
-        compare_with_fixture(g, fixture(name, n), fp64_tol(n), fp64_tol(n), f"{name} fp64 flags={flags} step {n}")
+        fx = fixture(name, n)
+        kappa = torque_condition(name, fx["w_mean"])
+        compare_with_fixture(g, fx, fp64_tol(n), fp64_tol(n), f"{name} fp64 flags={flags} step {n} "
+                             f"(wall-shear condition {kappa[0]:.0f} / {kappa[1]:.0f})", kappa=kappa, steps=n)
 
 
 @pytest.mark.parametrize("name", ["tc-medium-fp64", "tc-turbulent-fp64"])

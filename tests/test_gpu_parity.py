@@ -242,20 +242,52 @@ def test_turbulent_size_one_substep_sampled(flags):
     assert ev < TOL and ee < TOL
 
 
-@pytest.mark.parametrize("nz", [96, 256, 384])
+@pytest.mark.parametrize("nz", [96, 128, 256, 384])
 def test_paired_solve_layout_matches_oracle(nz):
     """The radial solve with the two signs of l of each wavenumber pair in the
-    two halves of a wavefront (the default where the pairs fill at least 85 %
-    of the lanes): three steps against the oracle with one full group of 32
-    pairs per j (N_z = 96, K_z = 31), three groups the last of them partial
-    (N_z = 256, K_z = 85) and four full groups (N_z = 384, K_z = 127)."""
+    two halves of a wavefront (an autotuner candidate, set here through
+    tc_set_solve_shape): three steps against the oracle with one full group
+    of 32 pairs per j (N_z = 96, K_z = 31), two groups the second partial
+    (N_z = 128, K_z = 42), three groups the last partial (N_z = 256, K_z = 85)
+    and four full groups (N_z = 384, K_z = 127)."""
     w = workload("tc-small-fp64", nr=33, ntheta=12, nz=nz, amplitude=1e-2)
     orc, gpu = pair(w)
+    gpu.set_solve_shape(10000 + gpu.tuning()["solve_shape"])
     assert gpu.tuning()["solve_shape"] >= 10000
     for s in range(3):
         orc.step(1)
         gpu.step(1)
         _compare_state(orc, gpu, label=f"paired nz={nz} step {s + 1}")
+
+
+@pytest.mark.parametrize("name", ["tc-medium-fp64", "tc-turbulent-fp64"])
+def test_tile_shapes_are_bit_identical(name):
+    """Every compiled tile shape of the transform kernels (z kernels at half,
+    the default and twice the columns per block; theta at 1, 2 and 4
+    wavefronts per block) gives the default's products bit for bit, in both
+    precisions; a shape that is not compiled is refused."""
+    from tests.helpers import abi_geometry, fields_for
+    w = workload(name)
+    for prec in (tcb.TC_PREC_FP64, tcb.TC_PREC_MIXED):
+        g = tcb.Solver(abi_geometry(w, prec))
+        g.load_fields(*fields_for(w, g.grid()))
+        want = g.products()
+        tried = 0
+        for zi, th, zf in ((1, 0, 1), (2, 0, 2), (0, 1, 0), (0, 2, 0), (0, 3, 0)):
+            try:
+                g.set_tiles(zi, th, zf)
+            except tcb.TcError as e:
+                assert e.code == tcb.TC_EINVAL
+                continue
+            assert g.tiles() == {"zinv": zi, "theta": th, "zfwd": zf}
+            got = g.products()
+            tried += 1
+            for k in want:
+                assert np.array_equal(got[k], want[k]), (name, prec, zi, th, zf, k)
+        assert tried >= 3
+        with pytest.raises(tcb.TcError):
+            g.set_tiles(0, 7, 0)
+        g.close()
 
 
 def test_loaded_field_validation():
@@ -565,6 +597,8 @@ def test_autotune_keeps_the_state_and_the_results():
         assert np.array_equal(x, y)
     t = gpu.tuning()
     assert t["rhs_rows"] in (6, 11, 16, 21) and t["solve_shape"] % 10000 in (804, 808, 1608)
+    tl = gpu.tiles()
+    assert tl["zinv"] in (0, 1, 2) and tl["zfwd"] in (0, 1, 2) and tl["theta"] in (0, 1, 2, 3)
     orc.step(2)
     gpu.step(2)
     _compare_state(orc, gpu, label="after autotune")
@@ -577,6 +611,7 @@ def test_autotune_keeps_the_state_and_the_results():
     for i, x in enumerate(ws):
         ref.load_fields(*fields_for(x, ref.grid(i)), inst=i)
     multi.autotune(2)
+    print("tiles chosen:", [multi.tiles(i) for i in range(len(ws))], flush=True)
     multi.step(2)
     ref.step(2)
     for i in range(len(ws)):
