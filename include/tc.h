@@ -255,15 +255,22 @@ int tc_set_solve_shape(tc_ctx* ctx, int inst, int code);
 /* Set the tile shapes of the transform stages (codes as tc_tiles reports)
  * for every instance that shares instance `inst`'s launch of each stage.
  * TC_EINVAL if a shape is not compiled for the stage's transform length and
- * precision.  Results are bit-identical for every tile shape.  The step graph
- * is recaptured on the next tc_step. */
+ * precision.  Results are bit-identical for every tile shape (theta codes 4
+ * and 5 select other transforms: equal to rounding).  The step graph is
+ * recaptured on the next tc_step. */
 int tc_set_tiles(tc_ctx* ctx, int inst, int zinv, int theta, int zfwd);
 
 /* The tile shapes of the transform stages in use for instance `inst` (after
  * tc_create: 0 everywhere, the defaults; after tc_autotune: the choice of the
  * instance's launch group).  z kernels (inverse and forward): 0 the default
  * columns per block, 1 half of them, 2 twice; theta kernel: 0 the default
- * wavefronts per block, 1, 2 or 3 for 1, 2 or 4.  Any pointer may be NULL. */
+ * wavefronts per block, 1, 2 or 3 for 1, 2 or 4.  At N_theta = 768, where
+ * the default theta transform swaps lane digits (two of them through LDS,
+ * one in registers), theta code 4 selects the Stockham transform through LDS
+ * and code 5 the transform with every exchange in registers, both at the
+ * default wavefronts per block; these two give the default's products to
+ * rounding, not bit for bit, and the autotuner does not pick them.  Any
+ * pointer may be NULL. */
 int tc_tiles(const tc_ctx* ctx, int inst, int* zinv, int* theta, int* zfwd);
 
 /* Per-kernel timing with HIP events on the context's stream.

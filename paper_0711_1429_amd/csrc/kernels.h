@@ -101,7 +101,8 @@ struct DevGeom {
     int generic_fft;        // 1: run-time-length FFT kernels even for compiled lengths
     int tile_zinv;          // tile shape of the fixed-length z kernels: 0 default columns per
     int tile_zfwd;          //   block, 1 half, 2 twice (when that shape is compiled)
-    int tile_theta;         // theta kernel wavefronts per block: 0 default, 1, 2, 3 for 1, 2, 4
+    int tile_theta;         // theta kernel wavefronts per block: 0 default, 1, 2, 3 for 1, 2, 4;
+                            //   at N_theta = 768 also 4 (Stockham transform), 5 (register exchanges)
     int linear;             // 1: no products (the transform stages are not launched)
 };
 

@@ -27,6 +27,7 @@
 #include <mutex>
 
 #include "fft_lane.h"
+#include "fft_xlane.h"
 #include "kernels.h"
 
 namespace tc {
@@ -1669,9 +1670,13 @@ constexpr int theta_waves() { return sizeof(T) == 8 ? 1 : 2; }
 // and does everything for them.  It loads u, v and w, inverse-transforms them
 // in turn (the results stay in registers, in the same slot order for all
 // three), forms each of the six products pointwise in registers and
-// forward-transforms it through its own LDS region.  The wavefronts of a
-// block share only the twiddle table, so no block-wide barrier follows it.
-template <typename T, int N, int WV>
+// forward-transforms it.  The wavefronts of a block share only the twiddle
+// table, so no block-wide barrier follows it.  XM selects the transform:
+// 0 the Stockham passes through the wavefront's own LDS region (fft_lane.h);
+// for N = 768 (fft_xlane.h) 1 every exchange between lanes in registers, 2
+// the highest lane digit swapped in registers and the two lower ones through
+// a small LDS buffer.
+template <typename T, int N, int WV, int XM>
 __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) void k_theta_wave(
     const InstDev* __restrict__ I) {
     const DevGeom g = I[blockIdx.z].g;
@@ -1680,8 +1685,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     auto* __restrict__ pb = glb((C<T>*)b.pb);
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
-    __shared__ C<T> lds[WV * W * N];
-    __shared__ C<T> twl[lane::tw_size<N>() + 1];  // per-pass twiddles
+    constexpr bool XL = XM != 0;
+    static_assert(!XL || (N == xlane::N && TL == 64), "the register-exchange transform is 768 points per wavefront");
+    __shared__ C<T> lds[XM == 0 ? WV * W * N : (XM == 2 ? WV * xlane::XBUF : 1)];
+    __shared__ C<T> twl[XL ? xlane::NTW : lane::tw_size<N>() + 1];  // twiddles
     if ((int)blockIdx.y >= g.nr || (int)blockIdx.x * WV * W >= g.nz / 2) return;  // whole block
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lw = threadIdx.x & 63;
@@ -1692,7 +1699,22 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     const bool active = rp < nz / 2;
     const int r = blockIdx.y;
     const int z0 = 2 * rp;
-    lane::fill_twiddles<T, N>(twl, glb(tw_t<T>(g)), threadIdx.x, 64 * WV);
+    if constexpr (XL) {
+        if (threadIdx.x < 64) xlane::fill_twiddles<T>(twl, glb(tw_t<T>(g)), lw);
+    } else {
+        lane::fill_twiddles<T, N>(twl, glb(tw_t<T>(g)), threadIdx.x, 64 * WV);
+    }
+    const xlane::LaneBits lbits(lw);
+    // slot of position gl + TL m after a transform that leaves natural order
+    auto slot = [](int m) { return XL ? m : m_to_last_slot<N>(m); };
+    auto inverse = [&](C<T>* x) {
+        if constexpr (XL) xlane::inverse<T, XM == 2>(x, twl, lds + wv * xlane::XBUF, lw, lbits, WaveSync());
+        else lane::fft<T, N, +1, true>(lds + (wv * W + grp) * N, x, gl, twl, WaveSync());
+    };
+    auto forward = [&](C<T>* x) {
+        if constexpr (XL) xlane::forward<T, XM == 2>(x, twl, lds + wv * xlane::XBUF, lw, lbits, WaveSync());
+        else lane::fft<T, N, -1, true>(lds + (wv * W + grp) * N, x, gl, twl, WaveSync());
+    };
     // the z-spectral rows of field fl packed into the complex sequence of the
     // two real rows (z0, z0 + 1).  K_theta = (N - 1) / 3 is fixed by N, so
     // which of the kept band, the zero band and the mirrored band a register
@@ -1724,8 +1746,6 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
             x[k] = h;
         }
     };
-    C<T>* mine = lds + (wv * W + grp) * N;
-    const WaveSync sync;
     // forward-transform product x (slot order of the inverse transforms) and
     // write its two z rows.  The transform's outputs stay in registers: lane
     // gl holds positions gl + TL m, and the mirrored position N - j of its
@@ -1737,13 +1757,13 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     auto product_out = [&](int prod, const C<T>* a, const C<T>* c) {
         C<T> x[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = pmul(a[m_to_last_slot<N>(k)], c[m_to_last_slot<N>(k)]);
-        lane::fft<T, N, -1, true>(mine, x, gl, twl, sync);
+        for (int k = 0; k < P; ++k) x[k] = pmul(a[slot(k)], c[slot(k)]);
+        forward(x);
         C<T> hm[QN];
 #pragma unroll
         for (int q = 0; q < QN; ++q) {
-            const C<T> got = lane_read(x[m_to_last_slot<N>(P - 1 - q)], partner);
-            hm[q] = gl == 0 ? x[m_to_last_slot<N>((P - q) % P)] : got;
+            const C<T> got = lane_read(x[slot(P - 1 - q)], partner);
+            hm[q] = gl == 0 ? x[slot((P - q) % P)] : got;
         }
         if (active) {
             auto* out = pb + (((size_t)prod * nr + r) * nz + z0) * NJ;
@@ -1752,7 +1772,7 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
             for (int q = 0; q < QN; ++q) {
                 const int j = gl + q * TL;
                 if ((q + 1) * TL <= NJ || j < NJ) {
-                    const C<T> h = x[m_to_last_slot<N>(q)];
+                    const C<T> h = x[slot(q)];
                     at(out, (unsigned)j) = C<T>{(T)0.5 * (h.x + hm[q].x), (T)0.5 * (h.y - hm[q].y)};
                     at(out, (unsigned)(NJ + j)) = C<T>{(T)0.5 * (h.y + hm[q].y), (T)0.5 * (hm[q].x - h.x)};
                 }
@@ -1765,13 +1785,13 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     load(0, u);
     load(1, v);
     __syncthreads();  // twiddle table complete
-    lane::fft<T, N, +1, true>(mine, u, gl, twl, sync);
-    lane::fft<T, N, +1, true>(mine, v, gl, twl, sync);
+    inverse(u);
+    inverse(v);
     product_out(0, u, u);
     product_out(1, u, v);
     product_out(3, v, v);
     load(2, w);  // after vv: loading it earlier keeps a fourth register set live
-    lane::fft<T, N, +1, true>(mine, w, gl, twl, sync);
+    inverse(w);
     product_out(2, u, w);
     product_out(4, v, w);
     product_out(5, w, w);
@@ -2045,22 +2065,37 @@ void zfwd_lane(const Batch& B, hipStream_t s) {
     else if (code == 2) zfwd_lane_v<T, N, 2>(B, s);
     else zfwd_lane_v<T, N, 0>(B, s);
 }
-template <typename T, int N, int WV>
+template <typename T, int N, int WV, int XM>
 void theta_lane_v(const Batch& B, hipStream_t s) {
     constexpr int RB = (64 / lane::Plan<N>::TL) * WV;  // row pairs per block
     dim3 grid((B.g.nz / 2 + RB - 1) / RB, B.g.nr, B.count);
-    hipLaunchKernelGGL((k_theta_wave<T, N, WV>), grid, dim3(64 * WV), 0, s, B.inst);
+    hipLaunchKernelGGL((k_theta_wave<T, N, WV, XM>), grid, dim3(64 * WV), 0, s, B.inst);
 }
+// the transform of the theta kernel: the lane-digit swaps (fft_xlane.h)
+// wherever one wavefront holds one transform of 12 points per lane
+template <int N>
+constexpr int theta_xm() { return N == xlane::N ? 2 : 0; }
 // theta tile code: 0 the default wavefronts per block (theta_waves), 1, 2 or
-// 4 explicitly (codes 1, 2, 3)
+// 4 explicitly (codes 1, 2, 3); where the lane-digit transform is the
+// default, code 4 runs the Stockham transform and code 5 the transform with
+// every swap in registers, at the default wavefronts
 template <typename T, int N>
 void theta_lane(const Batch& B, hipStream_t s) {
+    constexpr int XM = theta_xm<N>();
     switch (B.g.tile_theta) {
-        case 1: theta_lane_v<T, N, 1>(B, s); return;
-        case 2: theta_lane_v<T, N, 2>(B, s); return;
-        case 3: theta_lane_v<T, N, 4>(B, s); return;
+        case 1: theta_lane_v<T, N, 1, XM>(B, s); return;
+        case 2: theta_lane_v<T, N, 2, XM>(B, s); return;
+        case 3: theta_lane_v<T, N, 4, XM>(B, s); return;
+        case 4:
+        case 5:
+            if constexpr (XM != 0) {
+                if (B.g.tile_theta == 4) theta_lane_v<T, N, theta_waves<T>(), 0>(B, s);
+                else theta_lane_v<T, N, theta_waves<T>(), 1>(B, s);
+                return;
+            }
+            break;
     }
-    theta_lane_v<T, N, theta_waves<T>()>(B, s);
+    theta_lane_v<T, N, theta_waves<T>(), XM>(B, s);
 }
 
 template <typename T>
@@ -2107,7 +2142,7 @@ bool lane_length(int n) {
 
 template <typename T>
 bool tile_ok_t(int stage, int n, int code) {
-    if (stage == ST_THETA) return code >= 0 && code <= 3 && lane_length(n);
+    if (stage == ST_THETA) return lane_length(n) && ((code >= 0 && code <= 3) || (code <= 5 && n == xlane::N));
     switch (n) {
 #define TC_CASE(N) case N: return zlane_variant_ok<T, N>(code);
         TC_LANE_SIZES(TC_CASE)

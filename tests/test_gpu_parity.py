@@ -377,6 +377,34 @@ def test_lane_and_generic_paths_agree_at_turbulent_size():
         assert err < 1e-13
 
 
+def test_theta_transform_variants_agree_at_turbulent_size():
+    """The three 768-point theta transforms (lane-digit swaps with the low
+    digits through LDS, the default; Stockham passes through LDS, tile code 4;
+    every lane exchange in registers, tile code 5) give the same products to
+    the rounding of each precision (codes 0 and 5 differ only in how data move
+    between lanes, so they may agree bit for bit), and each code is refused at
+    a length where only the Stockham transform is compiled."""
+    w = workload("tc-turbulent-fp64")
+    from tests.helpers import abi_geometry, fields_for
+    for prec, tol in ((tcb.TC_PREC_FP64, 1e-13), (tcb.TC_PREC_MIXED, 2e-6)):
+        g = tcb.Solver(abi_geometry(w, prec))
+        g.load_fields(*fields_for(w, g.grid()))
+        ref = g.products()
+        for code in (4, 5):
+            g.set_tiles(0, code, 0)
+            got = g.products()
+            for k in ref:
+                err = rel_l2(got[k], ref[k])
+                print("theta code", code, prec, k, f"{err:.2e}", flush=True)
+                assert err < tol
+        g.close()
+    small = tcb.Solver(abi_geometry(workload("tc-medium-fp64")))
+    for code in (4, 5):
+        with pytest.raises(tcb.TcError):
+            small.set_tiles(0, code, 0)
+    small.close()
+
+
 def test_mixed_products_at_turbulent_size():
     """FP32 transforms on the full turbulent-case grid, the size at which the
     FP32 z kernels pair their column groups across XCDs, give the products of
