@@ -81,7 +81,7 @@ def measured_traffic(workload, precision, kernel):
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for f in ("kernels.hip", "fft_lane.h", "kernels.h"):
+    for f in ("kernels.hip", "fft_lane.h", "fft_xlane.h", "kernels.h"):
         with open(os.path.join(ROOT, "paper_0711_1429_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     sha, rows = None, {}
