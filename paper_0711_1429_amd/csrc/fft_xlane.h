@@ -1,6 +1,8 @@
-// 768-point transform held by one wavefront, with every exchange between
-// lanes done in registers (DPP moves inside rows of 16 lanes, permlane swaps
-// across rows) instead of through LDS.
+// 768-point transform held by one wavefront whose exchanges between lanes
+// are swaps of a 2-bit digit of the lane index with two bits of the register
+// slot index: the highest digit in registers (permlane swaps across rows of 16
+// lanes), the two lower digits either in registers too (DPP moves inside
+// rows) or through a small LDS buffer (LOW_LDS, what the theta kernel uses).
 //
 // Lane g (0..63) holds 12 complex points in slots s = 4 grp + q (grp = 0..2,
 // q = 0..3).  Write g = c + 4 d + 16 h with the 2-bit digits c, d, h.
