@@ -199,6 +199,17 @@ int tc_stats(tc_ctx* ctx, int inst, tc_stats_t* out);
  * are always launched eagerly. */
 int tc_use_graphs(tc_ctx* ctx, int enable);
 
+/* Where the forward elimination of the Crank--Nicolson solves runs (Sec. 2.1;
+ * Appendix, boundary conditions).  enable = 1 (the default): for a context of
+ * one instance whose explicit-term kernel takes each column whole (tc_tuning's
+ * rhs_rows = N_r - 4), N_r <= 256 and a segmented solve, the explicit-term
+ * kernel eliminates each column as its right-hand-side rows complete and the
+ * solve only substitutes back; otherwise, and with enable = 0, the solve does
+ * both.  The two forms solve the same systems (results equal to rounding).
+ * The step graph is recaptured on the next tc_step.  TC_EINVAL for a
+ * host-only context. */
+int tc_set_rhs_elimination(tc_ctx* ctx, int enable);
+
 /* tc_stats for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same statistics, from the same kernels in the same order (bit-identical

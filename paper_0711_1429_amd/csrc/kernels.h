@@ -104,6 +104,8 @@ struct DevGeom {
     int tile_theta;         // theta kernel wavefronts per block: 0 default, 1, 2, 3 for 1, 2, 4;
                             //   at N_theta = 768 also 4 (Stockham transform), 5 (register exchanges)
     int linear;             // 1: no products (the transform stages are not launched)
+    int rhs_fwd;            // 1: the explicit-term kernel (one chunk per column) also runs the
+                            //   solve's forward elimination; the segmented solve only substitutes back
 };
 
 // Coefficients of one substep of the low-storage RK3 / Crank--Nicolson
@@ -185,6 +187,10 @@ long long stage_key(int stage, const DevGeom& g);
 // rows per chunk of the RHS kernel for an instance launched with `waves`
 // wavefronts per chunk row in total
 int rhs_rows(int nr, int P, long long waves_per_chunk_row, bool fp32);
+// whether the explicit-term launch of g can also run the solve's forward
+// elimination (DevGeom::rhs_fwd): one chunk per column, N_r at most one block
+// of mean rows, a segmented solve
+bool rhs_fwd_ok(const DevGeom& g);
 // the default segment shape and lane layout of the radial solve, and whether
 // shape `code` is compiled and covers nr - 2 unknowns
 int solve_segment_rows(int nr, int kz);

@@ -597,6 +597,13 @@ __global__ __launch_bounds__(NT) void k_zfwd(const InstDev* __restrict__ I, int 
     }
 }
 
+// Index of the precomputed unpivoted LU factors of the Crank--Nicolson
+// systems: for substep k and equation e (0: v or the mean u, 1: eta or the
+// mean w), the fields {l2, l1, 1/u0, u1, u2} of every row and mode pair.
+__device__ __forceinline__ size_t lu_index(const DevGeom& g, int k, int eqn, int field, int i, int pair) {
+    return ((((size_t)k * 2 + eqn) * 5 + field) * g.nr + i) * g.npairs + pair;
+}
+
 // ---------------------------------------------------------------- k_rhs
 // One lane per (mode, chunk of rr consecutive rows of 2..nr-3, the rows
 // whose 5-point stencils are centred).  The lane walks the chunk's rr + 4
@@ -777,20 +784,74 @@ __device__ __forceinline__ C<TP> narrow(cd z) { return C<TP>{(TP)z.x, (TP)z.y}; 
 template <typename TP>
 __device__ __forceinline__ cd widen(C<TP> z) { return cd{(double)z.x, (double)z.y}; }
 
-// right-hand side of one row: (M + beta dt nu L) q + dt (gamma N + rho N_prev)
-template <typename TP, int K>
-__device__ __forceinline__ void rhs_store(TC_GLOBAL C<TP>* __restrict__ nv, TC_GLOBAL C<TP>* __restrict__ ne,
-                                          TC_GLOBAL cd* __restrict__ rv, TC_GLOBAL cd* __restrict__ re, size_t gid, bool vrow, const RhsAcc& A, cd pv,
-                                          cd pe, double dt, const StepCoef& sc) {
-    cd r = {0, 0};
+// right-hand side of one row: (M + beta dt nu L) q + dt (gamma N + rho N_prev),
+// r for v (zero on the wall-derivative rows, vrow false) and q for eta
+template <int K>
+__device__ __forceinline__ void rhs_values(const RhsAcc& A, bool vrow, cd pv, cd pe, double dt, const StepCoef& sc,
+                                           cd& r, cd& q) {
+    r = cd{0, 0};
     if (vrow) r = cfma(dt * sc.gamma, A.Nv, K > 0 ? cfma(dt * sc.rho, pv, A.Iv) : A.Iv);
-    const cd q = cfma(dt * sc.gamma, A.Ne, K > 0 ? cfma(dt * sc.rho, pe, A.Ie) : A.Ie);
+    q = cfma(dt * sc.gamma, A.Ne, K > 0 ? cfma(dt * sc.rho, pe, A.Ie) : A.Ie);
+}
+
+// the explicit terms of one row into the N registers of the next substep
+template <typename TP, int K>
+__device__ __forceinline__ void n_store(TC_GLOBAL C<TP>* __restrict__ nv, TC_GLOBAL C<TP>* __restrict__ ne, size_t gid,
+                                        bool vrow, const RhsAcc& A) {
     if (K < 2) {
         nv[gid] = narrow<TP>(vrow ? A.Nv : cd{0, 0});
         ne[gid] = narrow<TP>(A.Ne);
     }
+}
+
+template <typename TP, int K>
+__device__ __forceinline__ void rhs_store(TC_GLOBAL C<TP>* __restrict__ nv, TC_GLOBAL C<TP>* __restrict__ ne,
+                                          TC_GLOBAL cd* __restrict__ rv, TC_GLOBAL cd* __restrict__ re, size_t gid, bool vrow, const RhsAcc& A, cd pv,
+                                          cd pe, double dt, const StepCoef& sc) {
+    cd r, q;
+    rhs_values<K>(A, vrow, pv, pe, dt, sc, r, q);
+    n_store<TP, K>(nv, ne, gid, vrow, A);
     rv[gid] = r;
     re[gid] = q;
+}
+
+// The forward elimination of the Crank--Nicolson systems of v and eta run
+// along a column as its right-hand-side rows complete (rows in increasing
+// order): y_n = r_n - l1_n y_{n-1} - l2_n y_{n-2} with the precomputed factors
+// of the lane's pair, row 1 folded with the raw row 2 and row nr-2 with the
+// raw row nr-3 first (the same folds the solve would apply).  rv / re then
+// hold y and the solve only substitutes back.
+struct FwdState {
+    cd y1v, y2v, y1e, y2e;  // y_{n-1}, y_{n-2} of v and eta
+    cd rv_raw, re_raw;      // the last raw right-hand sides (row nr-3 when the walk ends)
+    double lv2, lv1, le2, le1;  // factors of the next row to complete
+};
+struct FwdArgs {
+    const TC_GLOBAL double* __restrict__ lv;  // l2 of eqn v at row 0 of the lane's pair (l1: + lfs)
+    const TC_GLOBAL double* __restrict__ le;  // the same for eta
+    size_t lfs, lrs;                          // field and row strides of the factor table
+    double f0v, f0e, f1v, f1e;                // fold factors of rows 1 and nr-2
+};
+__device__ __forceinline__ void fwd_fetch(FwdState& F, const FwdArgs& fa, int n) {
+    const size_t o = (size_t)max(n, 0) * fa.lrs;
+    F.lv2 = fa.lv[o];
+    F.lv1 = fa.lv[fa.lfs + o];
+    F.le2 = fa.le[o];
+    F.le1 = fa.le[fa.lfs + o];
+}
+// row n's raw (r, q) -> y, written to rv / re at gid
+__device__ __forceinline__ void fwd_row(FwdState& F, TC_GLOBAL cd* __restrict__ rv, TC_GLOBAL cd* __restrict__ re,
+                                        size_t gid, cd r, cd q, double lv2, double lv1, double le2, double le1) {
+    const cd yv = cfma(-lv2, F.y2v, cfma(-lv1, F.y1v, r));
+    const cd ye = cfma(-le2, F.y2e, cfma(-le1, F.y1e, q));
+    rv[gid] = yv;
+    re[gid] = ye;
+    F.y2v = F.y1v;
+    F.y1v = yv;
+    F.y2e = F.y1e;
+    F.y1e = ye;
+    F.rv_raw = r;
+    F.re_raw = q;
 }
 
 template <typename TP, int K>
@@ -822,7 +883,7 @@ __device__ __forceinline__ void pin_both(RhsAcc& A) {
 // a scheduling barrier closes every point, so the compiler neither hoists
 // further loads nor interleaves points (either would take the register count
 // above two waves per SIMD).
-template <typename TP, int K>
+template <typename TP, int K, bool FWD>
 __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, const TC_GLOBAL cd* __restrict__ eta,
                                          const TC_GLOBAL cd* __restrict__ dv, const TC_GLOBAL C<TP>* __restrict__ ps,
                                          const TC_GLOBAL C<TP>* __restrict__ pnv,
@@ -831,7 +892,7 @@ __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, con
                                          TC_GLOBAL cd* __restrict__ re, const TC_CONST double* __restrict__ coef,
                                          const TC_CONST double* __restrict__ r, int nr, int P, int mode, int n0, int rr,
                                          bool first, bool last, double mm, double al, double nu, double dt,
-                                         const StepCoef& sc) {
+                                         const StepCoef& sc, const FwdArgs& fa) {
     const size_t S = (size_t)nr * P;
     const size_t fs = (size_t)nr * 5;
     const double bdt = sc.beta * dt * nu;
@@ -844,6 +905,12 @@ __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, con
     RhsPoint<TP> nxt;
     rhs_load<TP>(v, eta, dv, ps, S, (size_t)max(n0 - 2 - pad, 0) * P + mode, nxt);
     cd pv = {0, 0}, pe = {0, 0};
+    FwdState F = {};
+    cd p1 = {0, 0};  // N_prev of eta at row 1 (FWD: row 1 is eliminated with row 2)
+    if constexpr (FWD) {
+        if (K > 0) p1 = widen<TP>(pne[(size_t)P + mode]);
+        fwd_fetch(F, fa, n0 - 4 - pad);
+    }
     // point mi = base + q - pad; the pad leading points (mi < 0, rows read
     // clamped to the grid) only feed accumulators of rows before the chunk,
     // which are never written, so row cc sits in slot (cc + pad) mod 5
@@ -862,6 +929,9 @@ __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, con
                 npv = widen<TP>(pnv[gid]);
                 npe = widen<TP>(pne[gid]);
             }
+            // factors of the row finished now (fetched one point earlier) and of the next
+            const double lv2 = F.lv2, lv1 = F.lv1, le2 = F.le2, le1 = F.le1;
+            if constexpr (FWD) fwd_fetch(F, fa, n0 + mi - 3);
             const RhsOps o = rhs_ops<TP>(cur, r[max(m, 0)], mm, al, nu, bdt);
 #pragma unroll
             for (int jj = 0; jj < 5; ++jj) {
@@ -881,25 +951,89 @@ __device__ __forceinline__ void rhs_lane(const TC_GLOBAL cd* __restrict__ v, con
                 rhs_acc_eta(W2, o, coef + (size_t)(nr - 2) * 5 + (mi - (T - 5)), fs, bdt);
                 pin_eta(W2);
             }
-            if (mi >= 4)  // row mi - 4 is complete
-                rhs_store<TP, K>(nnv, nne, rv, re, (size_t)(n0 + mi - 4) * P + mode, true, A[(q + 1) % 5], pv, pe, dt,
-                             sc);
+            if (mi >= 4) {  // row mi - 4 is complete
+                const size_t gid = (size_t)(n0 + mi - 4) * P + mode;
+                if constexpr (!FWD) {
+                    rhs_store<TP, K>(nnv, nne, rv, re, gid, true, A[(q + 1) % 5], pv, pe, dt, sc);
+                } else {
+                    cd r, qe;
+                    rhs_values<K>(A[(q + 1) % 5], true, pv, pe, dt, sc, r, qe);
+                    n_store<TP, K>(nnv, nne, gid, true, A[(q + 1) % 5]);
+                    if (mi == 4) {  // row 2; row 1 (points 0..4, all in) first, folded with it
+                        cd r1, q1;
+                        rhs_values<K>(W1, false, cd{0, 0}, p1, dt, sc, r1, q1);
+                        n_store<TP, K>(nnv, nne, (size_t)P + mode, false, W1);
+                        F.y1v = cfma(-fa.f0v, r, r1);
+                        F.y1e = cfma(-fa.f0e, qe, q1);
+                        rv[(size_t)P + mode] = F.y1v;
+                        re[(size_t)P + mode] = F.y1e;
+                    }
+                    fwd_row(F, rv, re, gid, r, qe, lv2, lv1, le2, le1);
+                }
+            }
             pv = npv;
             pe = npe;
             __builtin_amdgcn_sched_barrier(0);
         }
     }
     if (first) {
-        cd p1 = {0, 0};
-        if (K > 0) p1 = widen<TP>(pne[(size_t)P + mode]);
-        rhs_store<TP, K>(nnv, nne, rv, re, (size_t)P + mode, false, W1, cd{0, 0}, p1, dt, sc);
+        if constexpr (!FWD) {
+            if (K > 0) p1 = widen<TP>(pne[(size_t)P + mode]);
+            rhs_store<TP, K>(nnv, nne, rv, re, (size_t)P + mode, false, W1, cd{0, 0}, p1, dt, sc);
+        }
         rhs_zero_row<TP, K>(nnv, nne, rv, re, (size_t)mode);
     }
     if (last) {
         cd p2 = {0, 0};
         if (K > 0) p2 = widen<TP>(pne[(size_t)(nr - 2) * P + mode]);
-        rhs_store<TP, K>(nnv, nne, rv, re, (size_t)(nr - 2) * P + mode, false, W2, cd{0, 0}, p2, dt, sc);
+        if constexpr (!FWD) {
+            rhs_store<TP, K>(nnv, nne, rv, re, (size_t)(nr - 2) * P + mode, false, W2, cd{0, 0}, p2, dt, sc);
+        } else {  // row nr-2, folded with the raw row nr-3
+            cd r2, q2;
+            rhs_values<K>(W2, false, cd{0, 0}, p2, dt, sc, r2, q2);
+            n_store<TP, K>(nnv, nne, (size_t)(nr - 2) * P + mode, false, W2);
+            r2 = cfma(-fa.f1v, F.rv_raw, r2);
+            q2 = cfma(-fa.f1e, F.re_raw, q2);
+            fwd_fetch(F, fa, nr - 2);
+            fwd_row(F, rv, re, (size_t)(nr - 2) * P + mode, r2, q2, F.lv2, F.lv1, F.le2, F.le1);
+        }
         rhs_zero_row<TP, K>(nnv, nne, rv, re, (size_t)(nr - 1) * P + mode);
+    }
+}
+
+// FWD for the mean (0,0) mode, whose rows the mean blocks form one lane per
+// row: once they are all written, one lane runs the elimination of the two
+// mean-profile systems (wall values moved to the right-hand side, rows 1 and
+// nr-2 folded) down the column.
+template <int K>
+__device__ void mean_forward(const DevGeom& g, const DevBuf& b) {
+    const int nr = g.nr;
+    const size_t P = g.P;
+    const int mode = g.mean;
+    for (int eqn = 0; eqn < 2; ++eqn) {
+        cd* col = eqn == 0 ? b.rv : b.re;
+        const double* mw = b.mwall + ((size_t)K * 2 + eqn) * nr;
+        const double* lub = b.lu + lu_index(g, K, eqn, 0, 0, 0);  // pair 0 holds the mean systems
+        const size_t lfs = (size_t)nr * g.npairs;
+        const double f0 = b.fold[(((size_t)K * 2 + eqn) * 2 + 0) * g.npairs];
+        const double f1 = b.fold[(((size_t)K * 2 + eqn) * 2 + 1) * g.npairs];
+        auto raw = [&](int n) {
+            cd r = col[(size_t)n * P + mode];
+            r.x -= mw[n];
+            return r;
+        };
+        cd p1 = {0, 0}, p2 = {0, 0}, keep = {0, 0};
+        for (int n = 1; n <= nr - 2; ++n) {
+            cd rn = raw(n);
+            if (n == 1) rn = cfma(-f0, raw(2), rn);
+            if (n == nr - 2) rn = cfma(-f1, keep, rn);
+            if (n == nr - 3) keep = rn;
+            const double l2 = lub[(size_t)n * g.npairs], l1 = lub[lfs + (size_t)n * g.npairs];
+            const cd yn = cfma(-l2, p2, cfma(-l1, p1, rn));
+            col[(size_t)n * P + mode] = yn;
+            p2 = p1;
+            p1 = yn;
+        }
     }
 }
 
@@ -912,7 +1046,7 @@ constexpr int RHS_MAX_ROWS = 21;
 constexpr int RHS_MIN_WAVES = 4096;
 constexpr long long RHS_ONE_CHUNK_WAVES = 1000;
 
-template <typename TP, int K>
+template <typename TP, int K, bool FWD>
 __global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepCoef sc) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
@@ -921,6 +1055,10 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepC
     if (blockIdx.y == 1) {  // the mean (0,0) mode: one lane per row
         const int n = blockIdx.x * NT + threadIdx.x;
         if (n < g.nr) rhs_mean_row<TP, K>(g, b, ps, sc, n);
+        if constexpr (FWD) {  // every row is in block 0 (nr <= NT)
+            __syncthreads();
+            if (blockIdx.x == 0 && threadIdx.x == 0) mean_forward<K>(g, b);
+        }
         return;
     }
     const int P = g.P;
@@ -937,11 +1075,25 @@ __global__ __launch_bounds__(NT) void k_rhs(const InstDev* __restrict__ I, StepC
     const int j = mode / g.nl;
     const int li = mode - j * g.nl;
     using CT = C<TP>;
-    rhs_lane<TP, K>(glb(b.v), glb(b.eta), glb(b.dv), ps, glb(K > 0 ? (const CT*)b.nv[K > 0 ? K - 1 : 0] : nullptr),
+    FwdArgs fa = {};
+    if constexpr (FWD) {
+        const int lp = li >= g.kz ? li - g.kz : g.kz - li;
+        const int pair = j * (g.kz + 1) + lp;
+        fa.lv = glb(b.lu) + lu_index(g, K, 0, 0, 0, pair);
+        fa.le = glb(b.lu) + lu_index(g, K, 1, 0, 0, pair);
+        fa.lfs = (size_t)g.nr * g.npairs;
+        fa.lrs = (size_t)g.npairs;
+        const auto* fold = glb(b.fold);
+        fa.f0v = fold[(((size_t)K * 2 + 0) * 2 + 0) * g.npairs + pair];
+        fa.f1v = fold[(((size_t)K * 2 + 0) * 2 + 1) * g.npairs + pair];
+        fa.f0e = fold[(((size_t)K * 2 + 1) * 2 + 0) * g.npairs + pair];
+        fa.f1e = fold[(((size_t)K * 2 + 1) * 2 + 1) * g.npairs + pair];
+    }
+    rhs_lane<TP, K, FWD>(glb(b.v), glb(b.eta), glb(b.dv), ps, glb(K > 0 ? (const CT*)b.nv[K > 0 ? K - 1 : 0] : nullptr),
                     glb(K > 0 ? (const CT*)b.neta[K > 0 ? K - 1 : 0] : nullptr),
                     glb(K < 2 ? (CT*)b.nv[K < 2 ? K : 0] : nullptr), glb(K < 2 ? (CT*)b.neta[K < 2 ? K : 0] : nullptr),
                     glb(b.rv), glb(b.re), cst(g.coef), cst(g.r), nr, P, mode, n0, rr, first, last, glb(g.m)[j],
-                    glb(g.alpha)[li], g.nu, g.dt, sc);
+                    glb(g.alpha)[li], g.nu, g.dt, sc, fa);
 }
 
 // ---------------------------------------------------------------- k_solve
@@ -1006,12 +1158,8 @@ constexpr int SV_CH = 8;
 // ------------------------------------------------ precomputed elimination
 // The Crank--Nicolson matrices depend only on the mode pair, the equation and
 // the substep (through beta_k dt nu), not on the state: their unpivoted LU
-// factors are computed once per context.  lu holds, for substep k and
-// equation e, the fields {l2, l1, 1/u0, u1, u2} of every row and pair;
-// fold holds the two boundary-row folding factors.
-__device__ __forceinline__ size_t lu_index(const DevGeom& g, int k, int eqn, int field, int i, int pair) {
-    return ((((size_t)k * 2 + eqn) * 5 + field) * g.nr + i) * g.npairs + pair;
-}
+// factors are computed once per context (lu_index, with the explicit terms
+// above); fold holds the two boundary-row folding factors.
 
 __global__ __launch_bounds__(SOLVE_NT) void k_factor(DevGeom g, DevBuf b, StepCoef sc, int k) {
     const int pair = blockIdx.x * SOLVE_NT + threadIdx.x;
@@ -1213,15 +1361,20 @@ __global__ __launch_bounds__(SOLVE_NT) void k_solve_lu(const InstDev* __restrict
 // is fetched once instead of once per sign of l.
 __device__ __forceinline__ int solve_pair_groups(int kz) { return (kz + 32) / 32; }
 
-template <int L, int SV_SEGMENTS, bool PAIRED>
+//
+// BACK: the explicit-term kernel has already run the forward elimination
+// (with the boundary-row folds and the mean wall terms) along each column and
+// left y in rv / re; only the back substitution runs here.
+template <int L, int SV_SEGMENTS, bool PAIRED, bool BACK>
 __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* __restrict__ I, int k) {
     const DevGeom g = I[blockIdx.z].g;
     const DevBuf b = I[blockIdx.z].b;
     // end values and end responses of each segment, forward sweep (xc, hx)
     // and back substitution (xb, hb) in separate arrays, so the second
     // exchange needs no barrier before it
-    __shared__ cd xc[SV_SEGMENTS][2][64];
-    __shared__ double hx[SV_SEGMENTS][4][64];
+    constexpr int FS = BACK ? 1 : SV_SEGMENTS;
+    __shared__ cd xc[FS][2][64];
+    __shared__ double hx[FS][4][64];
     __shared__ cd xb[SV_SEGMENTS][2][64];
     __shared__ double hb[SV_SEGMENTS][4][64];
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -1278,7 +1431,12 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
         h1[i] = 0.0;
         h2[i] = 0.0;
     }
-    if (len > 0) {
+    if constexpr (BACK) {
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+            if (i < len) y[i] = rhs[(size_t)(s0 + i) * P + mode];
+    }
+    if (!BACK && len > 0) {
         cd r[L];
 #pragma unroll
         for (int i = 0; i < L; ++i) r[i] = raw(min(s0 + i, nr - 2));
@@ -1306,6 +1464,7 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
             }
         }
     }
+    if constexpr (!BACK) {
     xc[seg][0][lane] = y[L - 1];
     xc[seg][1][lane] = y[L - 2];
     hx[seg][0][lane] = h1[L - 1];
@@ -1324,6 +1483,7 @@ __global__ __launch_bounds__(64 * SV_SEGMENTS) void k_solve_seg(const InstDev* _
 #pragma unroll
         for (int i = 0; i < L; ++i)
             if (i < len) y[i] = cfma(h1[i], c1, cfma(h2[i], c2, y[i]));
+    }
     }
     // back substitution from zero carry-in, with the responses to x_{s1}, x_{s1+1}
     {
@@ -2210,6 +2370,11 @@ void launch_zfwd(const Batch& B, bool fp32, hipStream_t s) {
         hipLaunchKernelGGL(k_zfwd<double>, grid, dim3(NT), (size_t)jb * g.nz * sizeof(C<double>), s, B.inst, jb);
 }
 
+bool rhs_fwd_ok(const DevGeom& g) {
+    // whole columns per lane, the mean rows in one block, a segmented solve
+    return g.rhs_rr >= g.nr - 4 && g.nr <= NT && g.solve_seg != 0;
+}
+
 int rhs_rows(int nr, int P, long long waves_per_chunk_row, bool fp32) {
     // FP64 launches with a thousand or more wavefronts per chunk row walk each
     // column in one chunk (no halo; measured fastest at 129 x 65280 modes)
@@ -2231,9 +2396,15 @@ void launch_rhs_t(const Batch& B, const StepCoef& c, int k, hipStream_t s) {
     // grid.y = 1: the mean rows (ceil(nr / NT) of those blocks do work)
     const unsigned gx = (unsigned)std::max((total + NT - 1) / NT, (size_t)(g.nr + NT - 1) / NT);
     dim3 grid(gx, 2, B.count);
-    if (k == 0) hipLaunchKernelGGL((k_rhs<TP, 0>), grid, dim3(NT), 0, s, B.inst, c);
-    else if (k == 1) hipLaunchKernelGGL((k_rhs<TP, 1>), grid, dim3(NT), 0, s, B.inst, c);
-    else hipLaunchKernelGGL((k_rhs<TP, 2>), grid, dim3(NT), 0, s, B.inst, c);
+    if (g.rhs_fwd) {
+        if (k == 0) hipLaunchKernelGGL((k_rhs<TP, 0, true>), grid, dim3(NT), 0, s, B.inst, c);
+        else if (k == 1) hipLaunchKernelGGL((k_rhs<TP, 1, true>), grid, dim3(NT), 0, s, B.inst, c);
+        else hipLaunchKernelGGL((k_rhs<TP, 2, true>), grid, dim3(NT), 0, s, B.inst, c);
+        return;
+    }
+    if (k == 0) hipLaunchKernelGGL((k_rhs<TP, 0, false>), grid, dim3(NT), 0, s, B.inst, c);
+    else if (k == 1) hipLaunchKernelGGL((k_rhs<TP, 1, false>), grid, dim3(NT), 0, s, B.inst, c);
+    else hipLaunchKernelGGL((k_rhs<TP, 2, false>), grid, dim3(NT), 0, s, B.inst, c);
 }
 
 void launch_rhs(const Batch& B, bool fp32, const StepCoef& c, int k, hipStream_t s) {
@@ -2273,25 +2444,34 @@ bool solve_shape_fits(int code, int nr) {
     return (base / 100) * (base % 100) >= nr - 2;
 }
 
-void launch_solve(const Batch& B, int k, hipStream_t s) {
+// the segmented solve of shape B.g.solve_seg; false when the shape is not one
+template <bool BACK>
+static bool launch_solve_seg(const Batch& B, int k, hipStream_t s) {
     // grid.y selects the equation, grid.z the instance
     const dim3 gseg((B.g.P + 63) / 64, 2, B.count);
     // paired: B.g carries the largest nj and the largest K_z of the group
     const dim3 gpair(B.g.nj * ((B.g.kz + 32) / 32), 2, B.count);
     switch (B.g.solve_seg) {
-        case 804: hipLaunchKernelGGL((k_solve_seg<4, 8, false>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
-        case 808: hipLaunchKernelGGL((k_solve_seg<8, 8, false>), gseg, dim3(64 * 8), 0, s, B.inst, k); return;
-        case 1608: hipLaunchKernelGGL((k_solve_seg<8, 16, false>), gseg, dim3(64 * 16), 0, s, B.inst, k); return;
+        case 804: hipLaunchKernelGGL((k_solve_seg<4, 8, false, BACK>), gseg, dim3(64 * 8), 0, s, B.inst, k); return true;
+        case 808: hipLaunchKernelGGL((k_solve_seg<8, 8, false, BACK>), gseg, dim3(64 * 8), 0, s, B.inst, k); return true;
+        case 1608:
+            hipLaunchKernelGGL((k_solve_seg<8, 16, false, BACK>), gseg, dim3(64 * 16), 0, s, B.inst, k);
+            return true;
         case SOLVE_PAIRED + 804:
-            hipLaunchKernelGGL((k_solve_seg<4, 8, true>), gpair, dim3(64 * 8), 0, s, B.inst, k);
-            return;
+            hipLaunchKernelGGL((k_solve_seg<4, 8, true, BACK>), gpair, dim3(64 * 8), 0, s, B.inst, k);
+            return true;
         case SOLVE_PAIRED + 808:
-            hipLaunchKernelGGL((k_solve_seg<8, 8, true>), gpair, dim3(64 * 8), 0, s, B.inst, k);
-            return;
+            hipLaunchKernelGGL((k_solve_seg<8, 8, true, BACK>), gpair, dim3(64 * 8), 0, s, B.inst, k);
+            return true;
         case SOLVE_PAIRED + 1608:
-            hipLaunchKernelGGL((k_solve_seg<8, 16, true>), gpair, dim3(64 * 16), 0, s, B.inst, k);
-            return;
+            hipLaunchKernelGGL((k_solve_seg<8, 16, true, BACK>), gpair, dim3(64 * 16), 0, s, B.inst, k);
+            return true;
     }
+    return false;
+}
+
+void launch_solve(const Batch& B, int k, hipStream_t s) {
+    if (B.g.rhs_fwd ? launch_solve_seg<true>(B, k, s) : launch_solve_seg<false>(B, k, s)) return;
     dim3 grid((B.g.npairs + SOLVE_NT - 1) / SOLVE_NT, 2, B.count);
     hipLaunchKernelGGL(k_solve_lu, grid, dim3(SOLVE_NT), 0, s, B.inst, k);
 }

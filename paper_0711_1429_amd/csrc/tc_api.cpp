@@ -77,6 +77,7 @@ struct tc_ctx {
     std::vector<void*> allocs;          // class arrays
     double* hflags = nullptr;           // pinned: one non-finite flag per instance
     bool use_graphs = true;
+    bool rhs_elimination = true;        // forward elimination in the explicit-term kernel where it fits
     hipGraphExec_t step_graph = nullptr;  // one full step of every instance
     hipStream_t graph_stream = nullptr;
     bool dryrun = false;
@@ -414,9 +415,24 @@ int build_classes(tc_ctx* c) {
     return upload_descriptors(c);
 }
 
+// DevGeom::rhs_fwd of every instance and launch group from the current launch
+// parameters: on for a context of one instance whose explicit-term launch
+// takes whole columns and whose solve is segmented (rhs_fwd_ok).
+static void refresh_rhs_fwd(tc_ctx* c) {
+    const bool one = c->inst.size() == 1;
+    for (auto& in : c->inst) in.g.rhs_fwd = (c->rhs_elimination && one && rhs_fwd_ok(in.g)) ? 1 : 0;
+    for (int st = 0; st < ST_COUNT; ++st)
+        for (auto& gr : c->groups[st]) {
+            int f = 1;
+            for (int i : gr.members) f = f && c->inst[i].g.rhs_fwd;
+            gr.g.rhs_fwd = f;
+        }
+}
+
 // Copy every instance's current DevGeom/DevBuf into the device descriptor
 // arrays (after a change of a per-instance launch parameter).
 int upload_descriptors(tc_ctx* c) {
+    refresh_rhs_fwd(c);
     auto put = [&](const std::vector<int>& members, InstDev* dev) {
         std::vector<InstDev> host(members.size());
         for (size_t q = 0; q < members.size(); ++q) host[q] = InstDev{c->inst[members[q]].g, c->inst[members[q]].b};
@@ -885,6 +901,15 @@ int tc_kernel_times(tc_ctx* c, double* ms, long long* calls, int n) {
     return TC_OK;
 }
 
+int tc_set_rhs_elimination(tc_ctx* c, int enable) {
+    if (!c) return TC_EINVAL;
+    if (int rc = need_device(c)) return rc;
+    (void)hipStreamSynchronize(c->stream);
+    c->rhs_elimination = enable != 0;
+    drop_graph(c);
+    return upload_descriptors(c);
+}
+
 int tc_use_graphs(tc_ctx* c, int enable) {
     if (!c) return TC_EINVAL;
     if (int rc = need_device(c)) return rc;
@@ -932,12 +957,16 @@ int tc_autotune(tc_ctx* c, int repeats) {
     drop_graph(c);
     const bool was_timing = c->timing;
     c->timing = false;
+    // candidates are timed with the plain explicit-term and solve kernels
+    const bool was_elim = c->rhs_elimination;
+    c->rhs_elimination = false;
     // snapshot the state and the N registers; the tuning runs one substep to
     // fill every intermediate and then re-launches idempotent stages
     std::vector<void*> snap;
     auto cleanup = [&] {
         for (void* p : snap) (void)hipFree(p);
         c->timing = was_timing;
+        c->rhs_elimination = was_elim;
     };
     struct Copy {
         void* dst;
@@ -1054,6 +1083,7 @@ int tc_autotune(tc_ctx* c, int repeats) {
             }
         }
     }
+    c->rhs_elimination = was_elim;
     if (!rc) rc = upload_descriptors(c);
     // restore the state
     for (auto& cp : saved)
@@ -1177,10 +1207,13 @@ double tc_kernel_bytes(const tc_ctx* cc, int inst, int id) {
         case K_ZFWD: return 6.0 * t * Q + 6.0 * t * S;        // read 6; write 6 spectra
         case K_RHS:  // read v, eta, D v and 6 spectra, write the RHS of v and eta; the
                      // N registers (2 complex of the transform precision) are read by
-                     // substeps 2, 3 and written by 1, 2 (the average over a step is given)
-            return (48.0 + 6.0 * t + 2.0 * t * 2.0 / 3.0 + 2.0 * t * 2.0 / 3.0 + 32.0) * S;
-        case K_SOLVE:  // read RHS and the 5 LU fields of both equations, write v, eta
-            return 32.0 * S + 80.0 * in->s.nr * in->s.nj * (in->s.kz + 1.0) + 32.0 * S;
+                     // substeps 2, 3 and written by 1, 2 (the average over a step is given);
+                     // with the forward elimination also the l2, l1 fields of both equations
+            return (48.0 + 6.0 * t + 2.0 * t * 2.0 / 3.0 + 2.0 * t * 2.0 / 3.0 + 32.0) * S +
+                   (in->g.rhs_fwd ? 32.0 * in->s.nr * in->s.nj * (in->s.kz + 1.0) : 0.0);
+        case K_SOLVE:  // read RHS and the 5 LU fields of both equations (3 after the
+                       // forward elimination in the explicit-term kernel), write v, eta
+            return 32.0 * S + (in->g.rhs_fwd ? 48.0 : 80.0) * in->s.nr * in->s.nj * (in->s.kz + 1.0) + 32.0 * S;
         case K_ENERGY: return 48.0 * S;
         case K_FINITE: return 32.0 * S;
     }

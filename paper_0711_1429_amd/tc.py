@@ -81,6 +81,7 @@ _SIGNATURES = {
     "tc_stats_noalloc": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TcStats)]),
     "tc_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "tc_set_rhs_elimination": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
     "tc_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "tc_set_solve_shape": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -241,6 +242,9 @@ class Solver:
 
     def use_graphs(self, enable):
         self._check(self.lib.tc_use_graphs(self.ctx, int(bool(enable))))
+
+    def set_rhs_elimination(self, enable):
+        self._check(self.lib.tc_set_rhs_elimination(self.ctx, int(bool(enable))))
 
     def autotune(self, repeats=5):
         self._check(self.lib.tc_autotune(self.ctx, int(repeats)))

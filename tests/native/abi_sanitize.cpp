@@ -123,6 +123,7 @@ int main() {
         CHECK(tc_get_fields(c, 0, buf.data(), buf.data(), prof.data(), prof.data()) == TC_EINVAL);
         CHECK(tc_profiles(c, 0, prof.data()) == TC_EINVAL);
         CHECK(tc_use_graphs(c, 0) == TC_EINVAL);
+        CHECK(tc_set_rhs_elimination(c, 0) == TC_EINVAL);
         CHECK(tc_timing(c, 1) == TC_EINVAL);
         CHECK(tc_autotune(c, 1) == TC_EINVAL);
         CHECK(tc_set_stream(c, nullptr) == TC_EINVAL);

@@ -427,17 +427,50 @@ def test_mixed_products_at_turbulent_size():
         del m
 
 
+@pytest.mark.parametrize("prec", [tcb.TC_PREC_FP64, tcb.TC_PREC_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["tc-small-fp64", "tc-medium-fp64"])
+def test_forward_elimination_in_rhs_matches_oracle(name, prec):
+    """With whole-column chunks the explicit-term kernel runs the solves'
+    forward elimination along each column (boundary-row folds and the mean
+    profiles' wall terms included) and the solve substitutes back: three
+    steps against the oracle, in both precisions (mixed: the FP32 transform
+    error).  The solve's byte model drops the two factor fields it no longer
+    reads, which shows the form is in use; switched off, the solve does both
+    sweeps again."""
+    w = workload(name)
+    orc, gpu = pair(w, precision=prec)
+    nr = gpu.mode_shape()[0]
+    plain = gpu.kernel_bytes()["radial_solve"]
+    gpu.set_rhs_rows(nr - 4)
+    fused = gpu.kernel_bytes()["radial_solve"]
+    assert fused < plain
+    tol = TOL if prec == tcb.TC_PREC_FP64 else 1e-5
+    for s in range(3):
+        orc.step(1)
+        gpu.step(1)
+        _compare_state(orc, gpu, tol=tol, label=f"{name} fused elimination step {s + 1}")
+    gpu.set_rhs_elimination(False)
+    assert gpu.kernel_bytes()["radial_solve"] == plain
+    orc.step(1)
+    gpu.step(1)
+    _compare_state(orc, gpu, tol=tol, label=f"{name} after switching it off")
+
+
 @pytest.mark.parametrize("name", ["tc-small-fp64", "tc-medium-fp64"])
 def test_rhs_chunking_is_bit_identical(name):
     """The explicit-term kernel walks each radial column in chunks; every row's
     terms are summed in the same order whatever the chunk length, including
     lengths whose rr + 4 points are not whole periods of the rolled loop (the
     walk then starts up to 4 points early).  One step for each chunk length
-    gives the default's state bit for bit, in both precisions."""
+    gives the default's state bit for bit, in both precisions (with the
+    solve's forward elimination in the solve: whole-column chunks would
+    otherwise move it into the explicit-term kernel, which changes rounding;
+    that form has its own tests)."""
     from tests.helpers import abi_geometry, fields_for
     w = workload(name)
     for prec in (tcb.TC_PREC_FP64, tcb.TC_PREC_MIXED):
         ref = tcb.Solver(abi_geometry(w, prec))
+        ref.set_rhs_elimination(False)
         f = fields_for(w, ref.grid())
         ref.load_fields(*f)
         ref.step(1)
@@ -445,6 +478,7 @@ def test_rhs_chunking_is_bit_identical(name):
         nr = ref.mode_shape()[0]
         rows = sorted({1, 2, 3, 4, 7, 13, 22, 25, (nr - 4 + 1) // 2, nr - 4} & set(range(1, nr - 3)))
         g = tcb.Solver(abi_geometry(w, prec))
+        g.set_rhs_elimination(False)
         for rr in rows:
             g.set_rhs_rows(rr)
             assert g.tuning()["rhs_rows"] == rr
