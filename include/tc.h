@@ -280,8 +280,13 @@ int tc_set_tiles(tc_ctx* ctx, int inst, int zinv, int theta, int zfwd);
  * one in registers), theta code 4 selects the Stockham transform through LDS
  * and code 5 the transform with every exchange in registers, both at the
  * default wavefronts per block; these two give the default's products to
- * rounding, not bit for bit, and the autotuner does not pick them.  Any
- * pointer may be NULL. */
+ * rounding, not bit for bit, and the autotuner does not pick them.  Code 6
+ * keeps the lane-digit transform and fetches the third velocity field the
+ * other way (at this length FP64 loads it into registers by default and FP32
+ * has the memory unit copy it into LDS while the first two are transformed;
+ * code 6 swaps the two, at 2 wavefronts per block for the LDS form in FP64
+ * and the default for the register form in FP32): bit-identical, an
+ * autotuner candidate.  Any pointer may be NULL. */
 int tc_tiles(const tc_ctx* ctx, int inst, int* zinv, int* theta, int* zfwd);
 
 /* Per-kernel timing with HIP events on the context's stream.

@@ -243,24 +243,40 @@ template <int N>
 constexpr int tw_size() { return tw_offset(N, Plan<N>::NPASS); }
 
 // Fill the per-pass table from a full table of exp(+2 pi i e / N) (2N reals).
+// Each thread first loads its first entry of every pass (at a clamped index
+// where the pass has fewer entries than threads), then stores them, so those
+// loads are in flight together; entries beyond the first round follow.
 template <typename T, int N, int PASS, typename TwPtr>
-__host__ __device__ __forceinline__ void fill_pass(C<T>* twp, TwPtr tw_full, int tid, int nthreads) {
+__host__ __device__ __forceinline__ void fill_first(C<T>* first, TwPtr tw_full, int tid) {
+    if constexpr (PASS < Plan<N>::NPASS) {
+        constexpr int NS = ns_before(N, PASS);
+        constexpr int STEP = N / (NS * radices(N).r[PASS]);
+        const int e = (tid < NS ? tid : NS - 1) * STEP;
+        first[PASS] = C<T>{tw_full[2 * e], tw_full[2 * e + 1]};
+        fill_first<T, N, PASS + 1>(first, tw_full, tid);
+    }
+}
+template <typename T, int N, int PASS, typename TwPtr>
+__host__ __device__ __forceinline__ void fill_pass(C<T>* twp, const C<T>* first, TwPtr tw_full, int tid, int nthreads) {
     if constexpr (PASS < Plan<N>::NPASS) {
         constexpr int NS = ns_before(N, PASS);
         constexpr int STEP = N / (NS * radices(N).r[PASS]);
         constexpr int OFF = tw_offset(N, PASS);
-        for (int jm = tid; jm < NS; jm += nthreads) {
+        if (tid < NS) twp[OFF + tid] = first[PASS];
+        for (int jm = tid + nthreads; jm < NS; jm += nthreads) {
             const int e = jm * STEP;
             twp[OFF + jm] = C<T>{tw_full[2 * e], tw_full[2 * e + 1]};
         }
-        fill_pass<T, N, PASS + 1>(twp, tw_full, tid, nthreads);
+        fill_pass<T, N, PASS + 1>(twp, first, tw_full, tid, nthreads);
     }
 }
 
 // tw_full: any pointer-like to T (a device kernel passes a global-address-space pointer)
 template <typename T, int N, typename TwPtr>
 __host__ __device__ __forceinline__ void fill_twiddles(C<T>* twp, TwPtr tw_full, int tid, int nthreads) {
-    fill_pass<T, N, 1>(twp, tw_full, tid, nthreads);
+    C<T> first[Plan<N>::NPASS > 1 ? Plan<N>::NPASS : 1];
+    fill_first<T, N, 1>(first, tw_full, tid);
+    fill_pass<T, N, 1>(twp, first, tw_full, tid, nthreads);
 }
 
 // ------------------------------------------------------------------ passes

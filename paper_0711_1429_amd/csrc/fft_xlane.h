@@ -162,15 +162,25 @@ __device__ __forceinline__ void twiddle_groups(C<T>* x, const C<T>* tw, int g) {
 // shorter rows.
 template <typename T, typename TwPtr>
 __device__ __forceinline__ void fill_twiddles(C<T>* tw, TwPtr full, int g) {
+    // every lane loads all its entries (the short tables at a clamped index)
+    // before any is stored, so the loads are in flight together
     auto get = [&](int e) { return C<T>{full[2 * e], full[2 * e + 1]}; };
+    C<T> t0[P - 1], t1[3], t2[3];
 #pragma unroll
-    for (int n1 = 1; n1 < P; ++n1) tw[(n1 - 1) * 64 + g] = get((n1 * g) % N);
+    for (int n1 = 1; n1 < P; ++n1) t0[n1 - 1] = get((n1 * g) % N);
+#pragma unroll
+    for (int a = 1; a < 4; ++a) {
+        t1[a - 1] = get(12 * a * (g & 15));
+        t2[a - 1] = get(48 * a * (g & 3));
+    }
+#pragma unroll
+    for (int n1 = 1; n1 < P; ++n1) tw[(n1 - 1) * 64 + g] = t0[n1 - 1];
     if (g < 16)
 #pragma unroll
-        for (int a = 1; a < 4; ++a) tw[TW1 + (a - 1) * 16 + g] = get(12 * a * g);
+        for (int a = 1; a < 4; ++a) tw[TW1 + (a - 1) * 16 + g] = t1[a - 1];
     if (g < 4)
 #pragma unroll
-        for (int a = 1; a < 4; ++a) tw[TW2 + (a - 1) * 4 + g] = get(48 * a * g);
+        for (int a = 1; a < 4; ++a) tw[TW2 + (a - 1) * 4 + g] = t2[a - 1];
 }
 
 // The swap of the lane digit at bit D (0 or 2) with the slot digit through

@@ -188,16 +188,24 @@ __device__ __forceinline__ Wn wavecoef(double m, double al, double R) {
     return w;
 }
 
+// a = 1/k^2 = R^2 / (alpha^2 R^2 + m^2) of mode (m, alpha) at radius R.  Here
+// and in recover the multiply-adds are written as fused ones, so that every
+// kernel (and every tile shape of one) rounds them alike rather than as the
+// compiler's contraction of each instance happens to pair them.
+__device__ __forceinline__ double inv_k2(double R, double m, double al) {
+    return R * R / fma(al * al * R, R, m * m);
+}
+
 // u, w from v, eta and D v (continuity and the definition of eta):
 // u = (i alpha D_* v - (i m / R) eta) a,  w = ((i m / R) D_* v + i alpha eta) a.
 __device__ __forceinline__ void recover(cd v, cd eta, cd dv, double R, double m, double al, double a,
                                         cd& u, cd& w) {
     const cd ds = {dv.x + v.x / R, dv.y + v.y / R};
     const double mr = m / R;
-    u.x = (-al * ds.y + mr * eta.y) * a;
-    u.y = (al * ds.x - mr * eta.x) * a;
-    w.x = (-mr * ds.y - al * eta.y) * a;
-    w.y = (mr * ds.x + al * eta.x) * a;
+    u.x = fma(mr, eta.y, -(al * ds.y)) * a;
+    u.y = fma(al, ds.x, -(mr * eta.x)) * a;
+    w.x = fma(-mr, ds.y, -(al * eta.y)) * a;
+    w.y = fma(mr, ds.x, al * eta.x) * a;
 }
 
 // ---------------------------------------------------------------- k_dv
@@ -448,7 +456,7 @@ __global__ __launch_bounds__(NT) void k_zinv(const InstDev* __restrict__ I, int 
                     val = C<T>{(T)v[e].x, (T)v[e].y};
                 } else {
                     const double m = g.m[j], al = g.alpha[l + kz];
-                    const double a = R * R / (al * al * R * R + m * m);
+                    const double a = inv_k2(R, m, al);
                     cd u, w;
                     recover(v[e], eta[e], dv[e], R, m, al, a, u, w);
                     const cd s = f == 0 ? u : w;
@@ -1586,7 +1594,7 @@ __global__ __launch_bounds__(RED_NT) void k_energy(DevGeom g, DevBuf b) {
             e += g.wr[n] * d;
         } else {
             const double mm = g.m[j], al = g.alpha[li];
-            const double a = R * R / (al * al * R * R + mm * mm);
+            const double a = inv_k2(R, mm, al);
             cd u, w;
             recover(v, eta, b.dv[gid], R, mm, al, a, u, w);
             d = cj * (u.x * u.x + u.y * u.y + v.x * v.x + v.y * v.y + w.x * w.x + w.y * w.y);
@@ -1631,7 +1639,7 @@ __global__ __launch_bounds__(RED_NT) void k_profiles(DevGeom g, DevBuf b, double
         const size_t gid = (size_t)n * P + mode;
         const double cj = j == 0 ? 1.0 : 2.0;
         const double mm = g.m[j], al = g.alpha[li];
-        const double a = R * R / (al * al * R * R + mm * mm);
+        const double a = inv_k2(R, mm, al);
         const cd v = b.v[gid];
         cd u, w;
         recover(v, b.eta[gid], b.dv[gid], R, mm, al, a, u, w);
@@ -1821,8 +1829,9 @@ __host__ __device__ constexpr int m_to_last_slot(int m) {
     return 0;
 }
 
-// wavefronts per block of the theta kernel (measured best: 1 in FP64, so that
-// every wavefront starts and ends on its own, 2 in FP32)
+// wavefronts per block of the theta kernel with w loaded into registers
+// (measured best: 1 in FP64, so that every wavefront starts and ends on its
+// own, 2 in FP32)
 template <typename T>
 constexpr int theta_waves() { return sizeof(T) == 8 ? 1 : 2; }
 
@@ -1835,7 +1844,9 @@ constexpr int theta_waves() { return sizeof(T) == 8 ? 1 : 2; }
 // 0 the Stockham passes through the wavefront's own LDS region (fft_lane.h);
 // for N = 768 (fft_xlane.h) 1 every exchange between lanes in registers, 2
 // the highest lane digit swapped in registers and the two lower ones through
-// a small LDS buffer.
+// a small LDS buffer, 3 as 2 with the rows of w fetched into LDS by the
+// memory unit (16-byte LDS-DMA loads) while u and v are transformed, so that
+// they arrive without registers held for them.
 template <typename T, int N, int WV, int XM>
 __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) void k_theta_wave(
     const InstDev* __restrict__ I) {
@@ -1845,9 +1856,13 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     auto* __restrict__ pb = glb((C<T>*)b.pb);
     using PL = lane::Plan<N>;
     constexpr int TL = PL::TL, P = PL::P, W = 64 / TL;
-    constexpr bool XL = XM != 0;
+    constexpr bool XL = XM != 0, LOW_LDS = XM >= 2, WDMA = XM == 3;
     static_assert(!XL || (N == xlane::N && TL == 64), "the register-exchange transform is 768 points per wavefront");
-    __shared__ C<T> lds[XM == 0 ? WV * W * N : (XM == 2 ? WV * xlane::XBUF : 1)];
+    __shared__ C<T> lds[XM == 0 ? WV * W * N : (LOW_LDS ? WV * xlane::XBUF : 1)];
+    // w's two z rows per wavefront, in whole 1 KB DMA pieces (64 lanes x 16 bytes)
+    constexpr int KT_ = (N - 1) / 3, WBYTES = 2 * (KT_ + 1) * (int)sizeof(C<T>);
+    constexpr int WPIECES = (WBYTES + 1023) / 1024, WSTRIDE = WPIECES * 1024 / (int)sizeof(C<T>);
+    __shared__ __attribute__((aligned(16))) C<T> wl[WDMA ? WV * WSTRIDE : 1];
     __shared__ C<T> twl[XL ? xlane::NTW : lane::tw_size<N>() + 1];  // twiddles
     if ((int)blockIdx.y >= g.nr || (int)blockIdx.x * WV * W >= g.nz / 2) return;  // whole block
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -1859,20 +1874,15 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     const bool active = rp < nz / 2;
     const int r = blockIdx.y;
     const int z0 = 2 * rp;
-    if constexpr (XL) {
-        if (threadIdx.x < 64) xlane::fill_twiddles<T>(twl, glb(tw_t<T>(g)), lw);
-    } else {
-        lane::fill_twiddles<T, N>(twl, glb(tw_t<T>(g)), threadIdx.x, 64 * WV);
-    }
     const xlane::LaneBits lbits(lw);
     // slot of position gl + TL m after a transform that leaves natural order
     auto slot = [](int m) { return XL ? m : m_to_last_slot<N>(m); };
     auto inverse = [&](C<T>* x) {
-        if constexpr (XL) xlane::inverse<T, XM == 2>(x, twl, lds + wv * xlane::XBUF, lw, lbits, WaveSync());
+        if constexpr (XL) xlane::inverse<T, LOW_LDS>(x, twl, lds + wv * xlane::XBUF, lw, lbits, WaveSync());
         else lane::fft<T, N, +1, true>(lds + (wv * W + grp) * N, x, gl, twl, WaveSync());
     };
     auto forward = [&](C<T>* x) {
-        if constexpr (XL) xlane::forward<T, XM == 2>(x, twl, lds + wv * xlane::XBUF, lw, lbits, WaveSync());
+        if constexpr (XL) xlane::forward<T, LOW_LDS>(x, twl, lds + wv * xlane::XBUF, lw, lbits, WaveSync());
         else lane::fft<T, N, -1, true>(lds + (wv * W + grp) * N, x, gl, twl, WaveSync());
     };
     // the z-spectral rows of field fl packed into the complex sequence of the
@@ -1880,31 +1890,58 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     // which of the kept band, the zero band and the mirrored band a register
     // slot covers is known at compile time for every slot but one or two.
     constexpr int KT = (N - 1) / 3, NJ = KT + 1;
-    auto load = [&](int fl, C<T>* x) {
-        const auto* row0 = zb + (((size_t)fl * nr + r) * nz + z0) * NJ;
-        if constexpr (W == 1) row0 = uniform(row0);  // one row pair per wavefront
-        const auto* row1 = row0 + NJ;
+    // get0(p), get1(p): mode p of rows z0 and z0 + 1.  Every load is issued
+    // before any value is combined (a slot that covers part of a band loads
+    // at a valid index in every lane and selects afterwards), so the loads of
+    // a field are in flight together instead of one slot's after another's.
+    auto fetch = [&](auto get0, auto get1, C<T>* a, C<T>* c) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int p = gl + k * TL;
+            const bool low_all = k * TL + TL - 1 <= KT, low_none = k * TL > KT;
+            const bool high_all = k * TL >= N - KT, high_none = k * TL + TL - 1 < N - KT;
+            if (low_none && high_none) continue;
+            const bool lo = low_all || (!low_none && p <= KT);
+            const bool hi = high_all || (!high_none && p >= N - KT);
+            const unsigned idx = lo ? (unsigned)p : (hi ? (unsigned)(N - p) : 0u);
+            a[k] = get0(idx);
+            c[k] = get1(idx);
+        }
+    };
+    auto combine = [&](const C<T>* a, const C<T>* c, C<T>* x) {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int p = gl + k * TL;
             const bool low_all = k * TL + TL - 1 <= KT, low_none = k * TL > KT;
             const bool high_all = k * TL >= N - KT, high_none = k * TL + TL - 1 < N - KT;
             C<T> h = {(T)0, (T)0};
-            if (active) {
-                if (low_all || (!low_none && p <= KT)) {
-                    C<T> a = at(row0, (unsigned)p), c = at(row1, (unsigned)p);
-                    if (k == 0 && p == 0) {
-                        a.y = (T)0;
-                        c.y = (T)0;
-                    }
-                    h = C<T>{a.x - c.y, a.y + c.x};
-                } else if (high_all || (!high_none && p >= N - KT)) {
-                    const C<T> a = at(row0, (unsigned)(N - p)), c = at(row1, (unsigned)(N - p));
-                    h = C<T>{a.x + c.y, c.x - a.y};
+            if (!(low_none && high_none)) {
+                const bool lo = low_all || (!low_none && p <= KT);
+                const bool hi = high_all || (!high_none && p >= N - KT);
+                C<T> ak = a[k], ck = c[k];
+                if (k == 0 && p == 0) {
+                    ak.y = (T)0;
+                    ck.y = (T)0;
                 }
+                const C<T> hl = {ak.x - ck.y, ak.y + ck.x}, hh = {ak.x + ck.y, ck.x - ak.y};
+                h = lo ? hl : (hi ? hh : h);
+                if (!active) h = C<T>{(T)0, (T)0};
             }
             x[k] = h;
         }
+    };
+    // a row pair past the plane's end (a wavefront with no work) reads the
+    // plane's first pair and discards it, so the loads need no branch
+    const int z0c = active ? z0 : 0;
+    auto row_pair = [&](int fl) {
+        const auto* row0 = zb + (((size_t)fl * nr + r) * nz + z0c) * NJ;
+        if constexpr (W == 1) row0 = uniform(row0);  // one row pair per wavefront
+        return row0;
+    };
+    auto fetch_field = [&](int fl, C<T>* a, C<T>* c) {
+        const auto* row0 = row_pair(fl);
+        const auto* row1 = row0 + NJ;
+        fetch([&](unsigned p) { return at(row0, p); }, [&](unsigned p) { return at(row1, p); }, a, c);
     };
     // forward-transform product x (slot order of the inverse transforms) and
     // write its two z rows.  The transform's outputs stay in registers: lane
@@ -1942,15 +1979,49 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     // u and v first, w after the three products that need only u and v, so
     // that at most three transform-sized register sets are live at a time
     C<T> u[P], v[P], w[P];
-    load(0, u);
-    load(1, v);
+    if constexpr (XL) {
+        if (threadIdx.x < 64) xlane::fill_twiddles<T>(twl, glb(tw_t<T>(g)), lw);
+    } else {
+        lane::fill_twiddles<T, N>(twl, glb(tw_t<T>(g)), threadIdx.x, 64 * WV);
+    }
+    {
+        // the loads of u and v, all in flight together
+        C<T> au[P], cu[P], av[P], cv[P];
+        fetch_field(0, au, cu);
+        fetch_field(1, av, cv);
+        combine(au, cu, u);
+        combine(av, cv, v);
+    }
     __syncthreads();  // twiddle table complete
+    C<T>* const wrow = wl + wv * WSTRIDE;
+    if constexpr (WDMA) {
+        // issued after the barrier, which waits for every outstanding load;
+        // the compiler waits for them (vmcnt) before the first read of wl
+        static_assert(W == 1 && WBYTES <= WPIECES * 1024, "w rows per wavefront");
+        if (active) {
+            const auto* src = (const TC_GLOBAL char*)row_pair(2);
+#pragma unroll
+            for (int q = 0; q < WPIECES; ++q) {
+                const int off = q * 1024 + lw * 16;
+                if (off < WBYTES)
+                    __builtin_amdgcn_global_load_lds((const void*)(src + off),
+                                                     (__attribute__((address_space(3))) void*)(wrow + q * (1024 / (int)sizeof(C<T>))),
+                                                     16, 0, 0);
+            }
+        }
+    }
     inverse(u);
     inverse(v);
     product_out(0, u, u);
     product_out(1, u, v);
     product_out(3, v, v);
-    load(2, w);  // after vv: loading it earlier keeps a fourth register set live
+    // after vv: loading w into registers earlier keeps a fourth register set live
+    {
+        C<T> aw[P], cw[P];
+        if constexpr (WDMA) fetch([&](unsigned p) { return wrow[p]; }, [&](unsigned p) { return wrow[NJ + p]; }, aw, cw);
+        else fetch_field(2, aw, cw);
+        combine(aw, cw, w);
+    }
     inverse(w);
     product_out(2, u, w);
     product_out(4, v, w);
@@ -1993,40 +2064,90 @@ __global__ __launch_bounds__(JBV * lane::Plan<N>::TL) void k_zinv_lane(const Ins
     // guard the twiddle table and the transposed write-out, which cross columns
     const WaveSync sync;
     __shared__ C<T> twl[lane::tw_size<N>() + 1];
-    lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
     C<T> X[3][P];
-    const double mm = active ? glb(g.m)[j] : 0.0;
+    const int jc = active ? j : j0;  // a lane past the tile reads its block's first column
+    const double mm = glb(g.m)[jc];
     const auto* vr = v + (size_t)r * Pm;  // plane r
     const auto* er = eta + (size_t)r * Pm;
     const auto* dr = dv + (size_t)r * Pm;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
+    // slot k's band, its l (0 in the zero band: a valid mode, read and dropped)
+    // and the element's offset in the plane
+    auto band = [&](int k, bool& low, bool& high, int& l) {
         const int q = gl + k * TL;
         const bool low_all = k * TL + TL - 1 <= KZ, low_none = k * TL > KZ;
         const bool high_all = k * TL >= N - KZ, high_none = k * TL + TL - 1 < N - KZ;
-        const bool low = low_all || (!low_none && q <= KZ);
-        const bool high = !low && (high_all || (!high_none && q >= N - KZ));
-        const int l = low ? q : q - N;
+        low = low_all || (!low_none && q <= KZ);
+        high = !low && (high_all || (!high_none && q >= N - KZ));
+        l = low ? q : (high ? q - N : 0);
+    };
+    auto zero_band = [&](int k) { return k * TL > KZ && k * TL + TL - 1 < N - KZ; };
+    // slot k of u, v, w from the loaded v, eta, D v and alpha of its mode
+    auto slot = [&](int k, cd lv, cd le, cd ld, double al, double um, double wm) {
+        bool low, high;
+        int l;
+        band(k, low, high, l);
         C<T> xu = {(T)0, (T)0}, xv = xu, xw = xu;
-        if (active && (low || high)) {
-            const unsigned e = (unsigned)(j * NL + (l + KZ));
-            if (j == 0 && l == 0) {
-                xu.x = (T)umean[r];
-                xw.x = (T)wmean[r];
-            } else {
-                const double al = glb(g.alpha)[l + KZ];
-                const double a = R * R / (al * al * R * R + mm * mm);
-                const cd vv = at(vr, e);
-                cd u, w;
-                recover(vv, at(er, e), at(dr, e), R, mm, al, a, u, w);
-                xu = C<T>{(T)u.x, (T)u.y};
-                xv = C<T>{(T)vv.x, (T)vv.y};
-                xw = C<T>{(T)w.x, (T)w.y};
-            }
+        const double a = inv_k2(R, mm, al);
+        cd u, w;
+        recover(lv, le, ld, R, mm, al, a, u, w);
+        if (j == 0 && l == 0) {  // the mean mode: a is not finite there, and not used
+            xu = C<T>{(T)um, (T)0};
+            xw = C<T>{(T)wm, (T)0};
+        } else {
+            xu = C<T>{(T)u.x, (T)u.y};
+            xv = C<T>{(T)lv.x, (T)lv.y};
+            xw = C<T>{(T)w.x, (T)w.y};
         }
+        if (!(active && (low || high))) xu = xv = xw = C<T>{(T)0, (T)0};
         X[0][k] = xu;
         X[1][k] = xv;
         X[2][k] = xw;
+    };
+    auto load = [&](int k, cd& lv, cd& le, cd& ld, double& al) {
+        bool low, high;
+        int l;
+        band(k, low, high, l);
+        const unsigned e = (unsigned)(jc * NL + (l + KZ));
+        al = glb(g.alpha)[l + KZ];
+        lv = at(vr, e);
+        le = at(er, e);
+        ld = at(dr, e);
+    };
+    if constexpr (sizeof(T) == 8) {
+        // FP64 (two waves per SIMD): every load of the lane, then the twiddle
+        // table's, are issued before any value is combined, so they are in
+        // flight together instead of one slot's after another's
+        cd lv[P], le[P], ld[P];
+        double lal[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            if (!zero_band(k)) load(k, lv[k], le[k], ld[k], lal[k]);
+        const double um = umean[r], wm = wmean[r];
+        lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (zero_band(k)) {
+                X[0][k] = X[1][k] = X[2][k] = C<T>{(T)0, (T)0};
+                continue;
+            }
+            slot(k, lv[k], le[k], ld[k], lal[k], um, wm);
+        }
+    } else {
+        // FP32 (four waves per SIMD, which hide the latency of one slot's
+        // loads at a time; holding every slot's would cost the fourth wave)
+        lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
+        const double um = umean[r], wm = wmean[r];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (zero_band(k)) {
+                X[0][k] = X[1][k] = X[2][k] = C<T>{(T)0, (T)0};
+                continue;
+            }
+            cd lv, le, ld;
+            double al;
+            load(k, lv, le, ld, al);
+            slot(k, lv, le, ld, al, um, wm);
+        }
     }
     // transposed write-out: tile element e of this lane is idx = threadIdx.x +
     // e NTH, row z = idx / ncols and column cc = idx mod ncols, at these
@@ -2157,7 +2278,7 @@ __global__ __launch_bounds__(NT) void k_velocity(DevGeom g, DevBuf b, cd* __rest
     const int j = mode / g.nl;
     const int li = mode - j * g.nl;
     const double R = g.r[n], mm = g.m[j], al = g.alpha[li];
-    const double a = R * R / (al * al * R * R + mm * mm);
+    const double a = inv_k2(R, mm, al);
     cd u, w;
     recover(b.v[gid], b.eta[gid], b.dv[gid], R, mm, al, a, u, w);
     uo[gid] = u;
@@ -2232,30 +2353,44 @@ void theta_lane_v(const Batch& B, hipStream_t s) {
     hipLaunchKernelGGL((k_theta_wave<T, N, WV, XM>), grid, dim3(64 * WV), 0, s, B.inst);
 }
 // the transform of the theta kernel: the lane-digit swaps (fft_xlane.h)
-// wherever one wavefront holds one transform of 12 points per lane
-template <int N>
-constexpr int theta_xm() { return N == xlane::N ? 2 : 0; }
-// theta tile code: 0 the default wavefronts per block (theta_waves), 1, 2 or
-// 4 explicitly (codes 1, 2, 3); where the lane-digit transform is the
-// default, code 4 runs the Stockham transform and code 5 the transform with
-// every swap in registers, at the default wavefronts
+// wherever one wavefront holds one transform of 12 points per lane, with w
+// loaded into registers in FP64 and fetched into LDS by DMA in FP32 (measured
+// best: in FP32 the DMA form keeps four waves per SIMD, in FP64 both forms
+// run two and the register form is 1 % faster)
+template <typename T, int N>
+constexpr int theta_xm() { return N == xlane::N ? (sizeof(T) == 4 ? 3 : 2) : 0; }
+// the other form of w's fetch, and the wavefronts per block of each (the
+// DMA form needs at least two per block in FP64 for two waves per SIMD
+// within the LDS, four in FP32)
+template <typename T, int N>
+constexpr int theta_xm_alt() { return theta_xm<T, N>() == 3 ? 2 : 3; }
+template <typename T, int XM>
+constexpr int theta_waves_for() { return XM == 3 ? (sizeof(T) == 8 ? 2 : 4) : theta_waves<T>(); }
+// theta tile code: 0 the default wavefronts per block, 1, 2 or 4 explicitly
+// (codes 1, 2, 3); where the lane-digit transform is the default, code 4 runs
+// the Stockham transform and code 5 the transform with every swap in
+// registers, and code 6 the lane-digit transform with the other form of w's
+// fetch, each at its default wavefronts
 template <typename T, int N>
 void theta_lane(const Batch& B, hipStream_t s) {
-    constexpr int XM = theta_xm<N>();
+    constexpr int XM = theta_xm<T, N>();
     switch (B.g.tile_theta) {
         case 1: theta_lane_v<T, N, 1, XM>(B, s); return;
         case 2: theta_lane_v<T, N, 2, XM>(B, s); return;
         case 3: theta_lane_v<T, N, 4, XM>(B, s); return;
         case 4:
         case 5:
+        case 6:
             if constexpr (XM != 0) {
+                constexpr int XA = theta_xm_alt<T, N>();
                 if (B.g.tile_theta == 4) theta_lane_v<T, N, theta_waves<T>(), 0>(B, s);
-                else theta_lane_v<T, N, theta_waves<T>(), 1>(B, s);
+                else if (B.g.tile_theta == 5) theta_lane_v<T, N, theta_waves<T>(), 1>(B, s);
+                else theta_lane_v<T, N, theta_waves_for<T, XA>(), XA>(B, s);
                 return;
             }
             break;
     }
-    theta_lane_v<T, N, theta_waves<T>(), XM>(B, s);
+    theta_lane_v<T, N, theta_waves_for<T, XM>(), XM>(B, s);
 }
 
 template <typename T>
@@ -2302,7 +2437,7 @@ bool lane_length(int n) {
 
 template <typename T>
 bool tile_ok_t(int stage, int n, int code) {
-    if (stage == ST_THETA) return lane_length(n) && ((code >= 0 && code <= 3) || (code <= 5 && n == xlane::N));
+    if (stage == ST_THETA) return lane_length(n) && ((code >= 0 && code <= 3) || (code <= 6 && n == xlane::N));
     switch (n) {
 #define TC_CASE(N) case N: return zlane_variant_ok<T, N>(code);
         TC_LANE_SIZES(TC_CASE)
