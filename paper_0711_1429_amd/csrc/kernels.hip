@@ -2113,10 +2113,11 @@ __global__ __launch_bounds__(JBV * lane::Plan<N>::TL) void k_zinv_lane(const Ins
         le = at(er, e);
         ld = at(dr, e);
     };
-    if constexpr (sizeof(T) == 8) {
-        // FP64 (two waves per SIMD): every load of the lane, then the twiddle
-        // table's, are issued before any value is combined, so they are in
-        // flight together instead of one slot's after another's
+    if constexpr (sizeof(T) == 8 || N <= 128) {
+        // FP64 (two waves per SIMD), and the short FP32 transforms: every
+        // load of the lane, then the twiddle table's, are issued before any
+        // value is combined, so they are in flight together instead of one
+        // slot's after another's
         cd lv[P], le[P], ld[P];
         double lal[P];
 #pragma unroll
@@ -2133,8 +2134,9 @@ __global__ __launch_bounds__(JBV * lane::Plan<N>::TL) void k_zinv_lane(const Ins
             slot(k, lv[k], le[k], ld[k], lal[k], um, wm);
         }
     } else {
-        // FP32 (four waves per SIMD, which hide the latency of one slot's
-        // loads at a time; holding every slot's would cost the fourth wave)
+        // FP32 at 192 points and more (four waves per SIMD, which hide the
+        // latency of one slot's loads at a time; holding every slot's would
+        // cost the fourth wave)
         lane::fill_twiddles<T, N>(twl, tw, threadIdx.x, NTH);
         const double um = umean[r], wm = wmean[r];
 #pragma unroll
@@ -2231,16 +2233,9 @@ __global__ __launch_bounds__(JBV * lane::Plan<N>::TL) void k_zfwd_lane(const Ins
         const auto* in = uniform(pb + ((size_t)f * g.nr + r) * N * nj);
         // past the tile the load repeats the plane's first element (in
         // bounds) and the value is never stored (loff < 0 exactly where
-        // goff < 0).  In FP32 the raw value is kept, so the loads stay in
-        // flight until the next pass instead of being waited for here; in
-        // FP64 the same form makes the compiler restructure the loop with
-        // serialized waits (0.46 -> 0.81 ms), so the value is zeroed there
+        // goff < 0), so the raw values are kept and the loads stay in flight
 #pragma unroll
-        for (int e = 0; e < P; ++e) {
-            const C<T> t = at(in, (unsigned)max(goff[e], 0));
-            if constexpr (sizeof(T) == 8) nxt[e] = goff[e] >= 0 ? t : C<T>{(T)0, (T)0};
-            else nxt[e] = t;
-        }
+        for (int e = 0; e < P; ++e) nxt[e] = at(in, (unsigned)max(goff[e], 0));
     };
     fetch(0);
 #pragma unroll 1
@@ -2255,6 +2250,17 @@ __global__ __launch_bounds__(JBV * lane::Plan<N>::TL) void k_zfwd_lane(const Ins
         for (int k = 0; k < P; ++k) x[k] = active ? lds[c * PITCH + gl + k * TL] : C<T>{(T)0, (T)0};
         sync();
         lane::fft<T, N, -1, true>(lds + c * PITCH, x, gl, twl, sync);
+        if constexpr (sizeof(T) == 8) {
+            // Loads and stores share one wait counter: once this product's
+            // stores are issued, waiting for the next tile would wait for
+            // them too.  The next tile is therefore required here, after the
+            // transform and before the stores: an empty statement that takes
+            // its registers as inputs (it reads and writes no memory, and as
+            // a volatile statement it stays between the transform and the
+            // stores).
+#pragma unroll
+            for (int e = 0; e < P; ++e) asm volatile("" : : "v"(nxt[e].x), "v"(nxt[e].y));
+        }
         if (active) {
             auto* out = uniform(ps + (size_t)f * g.nr * Pm + (size_t)r * Pm);  // plane r of product f
 #pragma unroll
