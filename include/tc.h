@@ -285,8 +285,10 @@ int tc_set_tiles(tc_ctx* ctx, int inst, int zinv, int theta, int zfwd);
  * other way (at this length FP64 loads it into registers by default and FP32
  * has the memory unit copy it into LDS while the first two are transformed;
  * code 6 swaps the two, at 2 wavefronts per block for the LDS form in FP64
- * and the default for the register form in FP32): bit-identical, an
- * autotuner candidate.  Any pointer may be NULL. */
+ * and the default for the register form in FP32): the same arithmetic in
+ * another order of instructions, equal to rounding (the compiler may fuse
+ * multiply-adds differently), an autotuner candidate.  Any pointer may be
+ * NULL. */
 int tc_tiles(const tc_ctx* ctx, int inst, int* zinv, int* theta, int* zfwd);
 
 /* Per-kernel timing with HIP events on the context's stream.

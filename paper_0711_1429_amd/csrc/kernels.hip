@@ -2014,12 +2014,21 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     inverse(v);
     product_out(0, u, u);
     product_out(1, u, v);
-    product_out(3, v, v);
-    // after vv: loading w into registers earlier keeps a fourth register set live
     {
+        // With the lane-digit transform and w in registers (XM = 2), w's
+        // loads go out before vv is transformed and stored: loads and stores
+        // share one wait counter, which counts in issue order, so waiting for
+        // w then does not wait for vv's stores as well (the other forms have
+        // no registers to spare for it)
         C<T> aw[P], cw[P];
-        if constexpr (WDMA) fetch([&](unsigned p) { return wrow[p]; }, [&](unsigned p) { return wrow[NJ + p]; }, aw, cw);
-        else fetch_field(2, aw, cw);
+        if constexpr (XM == 2) {
+            fetch_field(2, aw, cw);
+            product_out(3, v, v);
+        } else {
+            product_out(3, v, v);
+            if constexpr (WDMA) fetch([&](unsigned p) { return wrow[p]; }, [&](unsigned p) { return wrow[NJ + p]; }, aw, cw);
+            else fetch_field(2, aw, cw);
+        }
         combine(aw, cw, w);
     }
     inverse(w);

@@ -1066,8 +1066,9 @@ int tc_autotune(tc_ctx* c, int repeats) {
             int& field = st == ST_ZINV ? gr.g.tile_zinv : (st == ST_THETA ? gr.g.tile_theta : gr.g.tile_zfwd);
             int best_code = field;
             double best = 1e30;
-            // (theta code 6, the other form of w's fetch, is bit-identical too;
-            // codes 4 and 5 change the rounding and are not candidates)
+            // (theta code 6, the other form of w's fetch, changes at most the
+            // rounding, as the solve's segment shapes do; codes 4 and 5 are
+            // other transforms and not candidates)
             for (int code : {0, 1, 2, 3, 6}) {
                 if (code == 6 && st != ST_THETA) continue;
                 if (!tile_variant_ok(st, gr.g, c->fp32, code)) continue;
