@@ -1859,8 +1859,12 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     constexpr bool XL = XM != 0, LOW_LDS = XM >= 2, WDMA = XM == 3;
     static_assert(!XL || (N == xlane::N && TL == 64), "the register-exchange transform is 768 points per wavefront");
     __shared__ C<T> lds[XM == 0 ? WV * W * N : (LOW_LDS ? WV * xlane::XBUF : 1)];
+    // K_theta = (N - 1) / 3 is fixed by N, so which of the kept band, the zero
+    // band and the mirrored band a register slot covers is known at compile
+    // time for every slot but one or two
+    constexpr int KT = (N - 1) / 3, NJ = KT + 1;
     // w's two z rows per wavefront, in whole 1 KB DMA pieces (64 lanes x 16 bytes)
-    constexpr int KT_ = (N - 1) / 3, WBYTES = 2 * (KT_ + 1) * (int)sizeof(C<T>);
+    constexpr int WBYTES = 2 * NJ * (int)sizeof(C<T>);
     constexpr int WPIECES = (WBYTES + 1023) / 1024, WSTRIDE = WPIECES * 1024 / (int)sizeof(C<T>);
     __shared__ __attribute__((aligned(16))) C<T> wl[WDMA ? WV * WSTRIDE : 1];
     __shared__ C<T> twl[XL ? xlane::NTW : lane::tw_size<N>() + 1];  // twiddles
@@ -1886,10 +1890,7 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
         else lane::fft<T, N, -1, true>(lds + (wv * W + grp) * N, x, gl, twl, WaveSync());
     };
     // the z-spectral rows of field fl packed into the complex sequence of the
-    // two real rows (z0, z0 + 1).  K_theta = (N - 1) / 3 is fixed by N, so
-    // which of the kept band, the zero band and the mirrored band a register
-    // slot covers is known at compile time for every slot but one or two.
-    constexpr int KT = (N - 1) / 3, NJ = KT + 1;
+    // two real rows (z0, z0 + 1)
     // get0(p), get1(p): mode p of rows z0 and z0 + 1.  Every load is issued
     // before any value is combined (a slot that covers part of a band loads
     // at a valid index in every lane and selects afterwards), so the loads of
