@@ -1924,8 +1924,12 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
                     ak.y = (T)0;
                     ck.y = (T)0;
                 }
-                const C<T> hl = {ak.x - ck.y, ak.y + ck.x}, hh = {ak.x + ck.y, ck.x - ak.y};
-                h = lo ? hl : (hi ? hh : h);
+                // selected component by component: a select between the two
+                // complex values as whole objects is compiled as a choice of
+                // address between two stack copies, in scratch memory
+                const T hlx = ak.x - ck.y, hly = ak.y + ck.x, hhx = ak.x + ck.y, hhy = ck.x - ak.y;
+                h.x = lo ? hlx : (hi ? hhx : (T)0);
+                h.y = lo ? hly : (hi ? hhy : (T)0);
                 if (!active) h = C<T>{(T)0, (T)0};
             }
             x[k] = h;
@@ -2015,21 +2019,12 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     inverse(v);
     product_out(0, u, u);
     product_out(1, u, v);
+    product_out(3, v, v);
+    // after vv: loading w into registers earlier keeps a fourth register set live
     {
-        // With the lane-digit transform and w in registers (XM = 2), w's
-        // loads go out before vv is transformed and stored: loads and stores
-        // share one wait counter, which counts in issue order, so waiting for
-        // w then does not wait for vv's stores as well (the other forms have
-        // no registers to spare for it)
         C<T> aw[P], cw[P];
-        if constexpr (XM == 2) {
-            fetch_field(2, aw, cw);
-            product_out(3, v, v);
-        } else {
-            product_out(3, v, v);
-            if constexpr (WDMA) fetch([&](unsigned p) { return wrow[p]; }, [&](unsigned p) { return wrow[NJ + p]; }, aw, cw);
-            else fetch_field(2, aw, cw);
-        }
+        if constexpr (WDMA) fetch([&](unsigned p) { return wrow[p]; }, [&](unsigned p) { return wrow[NJ + p]; }, aw, cw);
+        else fetch_field(2, aw, cw);
         combine(aw, cw, w);
     }
     inverse(w);
