@@ -2000,8 +2000,10 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(2))) vo
     __syncthreads();  // twiddle table complete
     C<T>* const wrow = wl + wv * WSTRIDE;
     if constexpr (WDMA) {
-        // issued after the barrier, which waits for every outstanding load;
-        // the compiler waits for them (vmcnt) before the first read of wl
+        // issued right after u's and v's loads.  The compiler waits for them
+        // (vmcnt) before the first read of wl; its wait counts do not tell
+        // DMA loads from ordinary ones, so the wait for u and v covers them
+        // too: w arrives in the same round trip, without registers held
         static_assert(W == 1 && WBYTES <= WPIECES * 1024, "w rows per wavefront");
         if (active) {
             const auto* src = (const TC_GLOBAL char*)row_pair(2);
