@@ -18,6 +18,11 @@ FLAGS = [
 ]
 
 
+# the compiler's per-kernel resource report of kernels.hip (registers,
+# spills, scratch, occupancy), kept beside the objects for the tests
+RESOURCES = os.path.join(HERE, "_build", "kernels.resource-usage.txt")
+
+
 def build(verbose=True):
     objs = []
     build_dir = os.path.join(HERE, "_build")
@@ -25,9 +30,21 @@ def build(verbose=True):
     for src in SOURCES:
         obj = os.path.join(build_dir, src + ".o")
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        report = src == "kernels.hip"
+        if report:
+            cmd += ["-Rpass-analysis=kernel-resource-usage", "-fno-caret-diagnostics"]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        res = subprocess.run(cmd, stderr=subprocess.PIPE, text=True)
+        remarks = [l for l in res.stderr.splitlines() if "kernel-resource-usage" in l]
+        other = [l for l in res.stderr.splitlines() if "kernel-resource-usage" not in l]
+        if other:
+            print("\n".join(other), file=sys.stderr, flush=True)
+        if res.returncode != 0:
+            raise subprocess.CalledProcessError(res.returncode, cmd)
+        if report:
+            with open(RESOURCES, "w") as f:
+                f.write("\n".join(remarks) + "\n")
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", *objs, "-o", tmp,
